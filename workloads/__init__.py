@@ -1,0 +1,132 @@
+"""Seeded synthetic inputs shared by the HIP path, the oracle, the tests and the bench.
+
+This module holds *data only*: gas parameters, the synthetic cross-section
+constants, the column configurations and seeded random particle arrays.  It
+contains none of the method's arithmetic (no push, no collision, no field
+solve); each backend turns a config dict into its own native struct and
+derives every physical quantity itself.
+
+Config keys (all SI unless noted):
+  gas           "Ne" | "Ar" (label only; masses and cross sections are explicit)
+  M_amu         atom / ion mass in atomic mass units
+  el_A, el_B    elastic cross section sigma_el = A + B * (eps/1 eV)**el_p  [m^2]
+  el_p          +0.5 or -0.5 (so that only sqrt is needed)
+  ex_U, ex_smax lumped excitation: threshold [eV], peak sigma [m^2] (Thomson-like
+                shape 4 smax (U/eps)(1 - U/eps), peak at eps = 2U)
+  iz_U, iz_smax ionization: threshold [eV], peak sigma [m^2] (same shape)
+  cx_sigma      constant ion-atom charge-exchange cross section [m^2]
+  opb_w         energy-sharing width of the ionization split [eV]
+  bc            "bounded" (grounded x=0, anode phi(L)=V, absorbing walls) |
+                "periodic" (reinjection, imposed mean field E0 = V/L)
+  n_cells, L    grid cells and column length [m]
+  V             anode voltage (bounded) or E0*L (periodic) [V]
+  p_torr, Tg    gas pressure [Torr] and temperature [K]
+  n0            initial plasma density [m^-3]
+  ppc           macroparticles per cell per species at t=0
+  Te0_eV, Ti0_K initial electron temperature [eV] and ion temperature [K]
+  wall_mode     "off" | "fixed": radial-loss sink with frequency nu_w [s^-1]
+  dt            electron time step [s]; ions advance every ion_subcycle steps
+  eps_cap       energy [eV] up to which the null-collision bound is taken
+  g_cap         relative-speed bound [m/s] of the ion null-collision method
+  energy_sharing "opb" | "equal" split of the ionization excess energy
+  poisson       1 = self-consistent field, 0 = imposed field only (swarm mode)
+  sort_interval steps between counting sorts (0 = never; no effect on physics)
+  capacity      particle-array capacity as a multiple of the initial count
+  seed          Philox key
+"""
+from __future__ import annotations
+
+import copy
+import numpy as np
+
+# Synthetic cross-section sets.  The forms follow the lumped-level description of
+# the paper (one excitation level, one ionization channel, constant ion charge
+# exchange); the numbers are this project's own order-of-magnitude choices, not
+# tabulated data.
+NEON = dict(gas="Ne", M_amu=20.1797,
+            el_A=1.0e-21, el_B=4.0e-21, el_p=0.5,
+            ex_U=16.6, ex_smax=1.6e-21,
+            iz_U=21.56, iz_smax=6.0e-21,
+            cx_sigma=4.0e-19, opb_w=24.0)
+
+ARGON = dict(gas="Ar", M_amu=39.948,
+             el_A=1.0e-21, el_B=2.0e-20, el_p=0.5,
+             ex_U=11.5, ex_smax=1.0e-20,
+             iz_U=15.76, iz_smax=2.5e-20,
+             cx_sigma=5.0e-19, opb_w=10.0)
+
+_COMMON = dict(p_torr=1.0, Tg=300.0, Te0_eV=2.0, Ti0_K=300.0,
+               wall_mode="fixed", nu_w=1.0e5, dt=1.0e-11, ion_subcycle=20,
+               eps_cap=100.0, g_cap=1.0e4, energy_sharing="opb", poisson=1,
+               sort_interval=20, capacity=1.25, seed=1)
+
+
+def _mk(gas: dict, **kw) -> dict:
+    c = dict(_COMMON)
+    c.update(gas)
+    c.update(kw)
+    return c
+
+
+def small_bounded(seed: int = 1) -> dict:
+    """Neon, 1 Torr, 4 cm, 400 cells, grounded cathode / 40 V anode (~10 V/cm),
+    n0 = 1e14 m^-3, 50 particles per cell per species (20k + 20k), radial sink
+    for a 1 cm radius, dt = 1e-11 s, ions every 20 steps, 2000 steps."""
+    return _mk(NEON, bc="bounded", n_cells=400, L=0.04, V=40.0, n0=1.0e14,
+               ppc=50, seed=seed)
+
+
+def column_20cm(seed: int = 1, ppc: int = 200) -> dict:
+    """Neon, 1 Torr, periodic 20 cm column, 2000 cells, 200 per cell per species
+    (400k + 400k), E0 = 10 V/cm, n0 = 1e15 m^-3."""
+    return _mk(NEON, bc="periodic", n_cells=2000, L=0.20, V=0.20 * 1000.0,
+               n0=1.0e15, ppc=ppc, seed=seed)
+
+
+def column_50cm(seed: int = 1, ppc: int = 1000) -> dict:
+    """Neon, 0.5 Torr, periodic 50 cm column, 5000 cells, 1000 per cell per
+    species (5M + 5M), E0 = 10 V/cm, n0 = 1e15 m^-3."""
+    return _mk(NEON, bc="periodic", n_cells=5000, L=0.50, V=0.50 * 1000.0,
+               p_torr=0.5, n0=1.0e15, ppc=ppc, seed=seed)
+
+
+def tiny(bc: str = "periodic", seed: int = 3, **kw) -> dict:
+    """Small column for oracle pins and fast parity cases (several tiles, ragged)."""
+    c = _mk(NEON, bc=bc, n_cells=kw.pop("n_cells", 37), L=kw.pop("L", 0.0037),
+            V=kw.pop("V", 3.7), n0=kw.pop("n0", 1.0e14), ppc=kw.pop("ppc", 29),
+            seed=seed)
+    c.update(kw)
+    return c
+
+
+def with_(cfg: dict, **kw) -> dict:
+    c = copy.deepcopy(cfg)
+    c.update(kw)
+    return c
+
+
+def random_positions(n: int, L: float, seed: int) -> np.ndarray:
+    """Uniform positions in [0, L) from a seeded numpy generator."""
+    rng = np.random.default_rng(seed)
+    x = rng.random(n) * L
+    x[x >= L] = 0.0
+    return x
+
+
+def random_state(n: int, L: float, sigma_v: float, seed: int, id0: int = 0):
+    """Seeded particle arrays (x, vx, vy, vz, id) for parity cases."""
+    rng = np.random.default_rng(seed)
+    x = rng.random(n) * L
+    x[x >= L] = 0.0
+    v = rng.normal(0.0, sigma_v, size=(3, n))
+    ids = (np.arange(n, dtype=np.uint64) + id0).astype(np.uint32)
+    perm = rng.permutation(n)
+    return x[perm], v[0][perm].copy(), v[1][perm].copy(), v[2][perm].copy(), ids[perm]
+
+
+def charge_profile(n_nodes: int, seed: int, scale: int = 1 << 36):
+    """Seeded int64 fixed-point node charges for field-solve cases."""
+    rng = np.random.default_rng(seed)
+    re = rng.integers(0, scale, size=n_nodes, dtype=np.int64)
+    ri = rng.integers(0, scale, size=n_nodes, dtype=np.int64)
+    return re, ri
