@@ -346,17 +346,20 @@ int pco_deposit(const pco_column* c, const double* x, int64_t n, int64_t* rho)
 
 /* ------------------------------------------------------------ field solve */
 /* Thomas algorithm for -phi[j-1] + 2 phi[j] - phi[j+1] = b[j], j = 1..m,
- * with the boundary values already folded into b (section II). */
-static void thomas(int m, const double* b, double* phi /* 1..m */)
+ * with the boundary values already folded into b (section II).  The sweeps
+ * run in x87 extended precision: in double their rounding error grows
+ * roughly with the square of the node count (about 1e-11 of max|E| at 8000
+ * nodes), too coarse for a reference. */
+static void thomas(int m, const long double* b, long double* phi /* 1..m */)
 {
-    double* cp = (double*)malloc((size_t)(m + 1) * sizeof(double));
-    double* bp = (double*)malloc((size_t)(m + 1) * sizeof(double));
-    cp[1] = -1.0 / 2.0;
-    bp[1] = b[1] / 2.0;
+    long double* cp = (long double*)malloc((size_t)(m + 1) * sizeof(long double));
+    long double* bp = (long double*)malloc((size_t)(m + 1) * sizeof(long double));
+    cp[1] = -1.0L / 2.0L;
+    bp[1] = b[1] / 2.0L;
     for (int j = 2; j <= m; ++j) {
-        double den = 2.0 + cp[j - 1];          /* 2 - (-1) * cp[j-1] */
-        cp[j] = -1.0 / den;
-        bp[j] = (b[j] + bp[j - 1]) / den;     /* (b - (-1) bp[j-1]) / den */
+        long double den = 2.0L + cp[j - 1];          /* 2 - (-1) * cp[j-1] */
+        cp[j] = -1.0L / den;
+        bp[j] = (b[j] + bp[j - 1]) / den;            /* (b - (-1) bp[j-1]) / den */
     }
     phi[m] = bp[m];
     for (int j = m - 1; j >= 1; --j) phi[j] = bp[j] - cp[j] * phi[j + 1];
@@ -369,43 +372,44 @@ int pco_solve_field(const pco_column* c, const int64_t* rho_e, const int64_t* rh
 {
     if (!c || !rho_e || !rho_i || !E) return -1;
     const int nc = c->nc, nn = c->nn;
-    double* phi = (double*)calloc((size_t)nn + 2, sizeof(double));
-    double* b = (double*)calloc((size_t)nn + 2, sizeof(double));
+    long double* phi = (long double*)calloc((size_t)nn + 2, sizeof(long double));
+    long double* b = (long double*)calloc((size_t)nn + 2, sizeof(long double));
     if (!phi || !b) { free(phi); free(b); return -3; }
     /* right-hand side dx^2 rho / eps0 with rho = e W Q 2^-32 / dx: dx fpc Q */
-    const double k = c->fpc * c->dx;
+    const long double k = (long double)c->fpc * (long double)c->dx;
+    const long double dx = c->dx, fpc = c->fpc;
     if (!c->periodic) {
         /* bounded: phi_0 = 0, phi_nc = V (section V, electrodes at both ends) */
-        for (int j = 1; j < nc; ++j) b[j] = k * (double)(rho_i[j] - rho_e[j]);
+        for (int j = 1; j < nc; ++j) b[j] = k * (long double)(rho_i[j] - rho_e[j]);
         b[nc - 1] += c->Vb;
         thomas(nc - 1, b, phi);
-        phi[0] = 0.0;
+        phi[0] = 0.0L;
         phi[nc] = c->Vb;
         /* E at nodes: centred difference inside; half-cell Gauss's law at the
          * two electrodes (reading) */
-        for (int j = 1; j < nc; ++j) E[j] = (phi[j - 1] - phi[j + 1]) / (2.0 * c->dx);
-        double eh0 = (phi[0] - phi[1]) / c->dx;
-        double ehN = (phi[nc - 1] - phi[nc]) / c->dx;
-        E[0] = eh0 - c->fpc * (double)(rho_i[0] - rho_e[0]);
-        E[nc] = ehN + c->fpc * (double)(rho_i[nc] - rho_e[nc]);
+        for (int j = 1; j < nc; ++j) E[j] = (double)((phi[j - 1] - phi[j + 1]) / (2.0L * dx));
+        long double eh0 = (phi[0] - phi[1]) / dx;
+        long double ehN = (phi[nc - 1] - phi[nc]) / dx;
+        E[0] = (double)(eh0 - fpc * (long double)(rho_i[0] - rho_e[0]));
+        E[nc] = (double)(ehN + fpc * (long double)(rho_i[nc] - rho_e[nc]));
     } else {
         /* periodic: neutralise the mean charge, gauge phi_0 = 0 (reading of the
          * periodic solve), then E = -E0 + E_sp (section II) */
-        double qs = 0.0;
         int64_t qt = 0;
         for (int j = 0; j < nc; ++j) qt += rho_i[j] - rho_e[j];
-        qs = (double)qt / (double)nc;
-        for (int j = 1; j < nc; ++j) b[j] = k * ((double)(rho_i[j] - rho_e[j]) - qs);
+        const long double qs = (long double)qt / (long double)nc;
+        for (int j = 1; j < nc; ++j) b[j] = k * ((long double)(rho_i[j] - rho_e[j]) - qs);
         thomas(nc - 1, b, phi);
-        phi[0] = 0.0;
-        phi[nc] = 0.0;
+        phi[0] = 0.0L;
+        phi[nc] = 0.0L;
         for (int j = 0; j < nc; ++j) {
-            double pm = j == 0 ? phi[nc - 1] : phi[j - 1];
-            double pp = phi[j + 1];
-            E[j] = -c->E0 + (pm - pp) / (2.0 * c->dx);
+            long double pm = j == 0 ? phi[nc - 1] : phi[j - 1];
+            long double pp = phi[j + 1];
+            E[j] = (double)(-(long double)c->E0 + (pm - pp) / (2.0L * dx));
         }
     }
-    if (phi_out) memcpy(phi_out, phi, (size_t)nn * sizeof(double));
+    if (phi_out)
+        for (int j = 0; j < nn; ++j) phi_out[j] = (double)phi[j];
     free(phi);
     free(b);
     return 0;

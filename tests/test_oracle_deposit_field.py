@@ -182,3 +182,40 @@ def test_field_bounded_random_vs_banded_and_gauss(nc):
     # Gauss's law over the whole column: eps0 (E_N - E_0) = total charge
     tot = fpc * float((ri - re).sum())
     assert abs((E[nc] - E[0]) - tot) <= 1e-9 * max(abs(tot), np.abs(E).max())
+
+
+def _exact_gauss_field(o, bc, re, ri, V):
+    """Exact rational solution of the three-point system, written as Gauss's
+    law over half cells (independent of the Thomas sweeps being pinned)."""
+    from fractions import Fraction as Fr
+    nc = o.nc
+    L = Fr(o.cfg["L"])
+    fpc = Fr(_fpc(o))
+    Q = [int(a) - int(b) for a, b in zip(ri, re)]
+    T = [0] * nc
+    for j in range(1, nc):
+        T[j] = T[j - 1] + Q[j]
+    if bc == "bounded":
+        eh0 = -Fr(V) / L - fpc * Fr(sum(T), nc)
+        Eh = [eh0 + fpc * t for t in T]
+        E = [Eh[0] - fpc * Q[0]] + [(Eh[j - 1] + Eh[j]) / 2 for j in range(1, nc)] + \
+            [Eh[nc - 1] + fpc * Q[nc]]
+    else:
+        qt = sum(Q)
+        Tp = [Fr(T[j]) - Fr(j * qt, nc) for j in range(nc)]
+        eh0 = -fpc * sum(Tp) / nc
+        Eh = [eh0 + fpc * t for t in Tp]
+        E = [-Fr(V) / L + (Eh[j - 1] + Eh[j]) / 2 for j in range(nc)]
+    return np.array([float(v) for v in E])
+
+
+@pytest.mark.parametrize("bc", ["bounded", "periodic"])
+@pytest.mark.parametrize("nc", [2000, 8000])
+def test_field_matches_exact_rational_solution(bc, nc):
+    # the Thomas reference must be far tighter than the 1e-12 parity bar
+    L = nc * 1e-4
+    o = _col(bc, n_cells=nc, L=L, V=L * 1000.0)
+    re, ri = W.charge_profile(o.nn, seed=1 + nc)
+    _, E = o.solve_field(re, ri)
+    Ex = _exact_gauss_field(o, bc, re, ri, L * 1000.0)
+    assert np.abs(E - Ex).max() <= 2e-14 * np.abs(Ex).max()
