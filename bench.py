@@ -1,0 +1,145 @@
+"""Throughput benchmark of the GPU PIC-MCC column step.
+
+python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME] [--no-cpu]
+
+Prints one JSON line.  A step is one full time step of the column (electron
+advance with collisions and fused deposit, ion advance on subcycle steps,
+compaction, ionization products, field solve, periodic sort).  `value` is
+particle-steps per second: electrons advanced plus ions advanced (ions only
+on their subcycle steps), over exactly K timed steps with the state resident
+in device memory.  `roofline` reports the electron advance kernel (the
+dominant kernel) against the HBM peak, its duration measured with HIP events
+on the library's stream during the same timed window.  `cpu_baseline` times
+the FP64 CPU oracle on a bounded sample of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+import workloads as W  # noqa: E402
+
+HBM_PEAK_GBS = 8000.0   # MI355X HBM3E, GB/s
+
+WORKLOADS = {
+    # Ne 1 Torr, periodic 20 cm, 2000 cells, 200 per cell per species (400k + 400k)
+    "column_20cm": lambda: W.column_20cm(),
+    # Ne 0.5 Torr, periodic 50 cm, 5000 cells, 1000 per cell per species (5M + 5M)
+    "column_50cm": lambda: W.column_50cm(),
+    # Ne 1 Torr, bounded 4 cm, 400 cells, 50 per cell per species (20k + 20k)
+    "small_bounded": lambda: W.small_bounded(),
+}
+
+
+def electron_bytes_per_step(p_null: float) -> float:
+    """Algorithmic HBM bytes per electron per step of the advance kernel:
+    read x, vx (FP64) and id (u32), write x, vx; collision candidates (a
+    fraction p_null) also read and write vy, vz."""
+    return 8 + 8 + 4 + 8 + 8 + p_null * 32.0
+
+
+def cpu_baseline(cfg: dict, steps: int) -> dict:
+    from oracle.pco import Oracle
+    o = Oracle(cfg)
+    n0e, n0i = o.count(0), o.count(1)
+    S = int(cfg["ion_subcycle"])
+    t0 = time.perf_counter()
+    o.step(steps)
+    dt = time.perf_counter() - t0
+    ne = 0.5 * (n0e + o.count(0)) * steps
+    ion_steps = sum(1 for k in range(steps) if k % S == 0)
+    ni = 0.5 * (n0i + o.count(1)) * ion_steps
+    return {"value": (ne + ni) / dt, "unit": "particle-steps/s", "cores": 1, "kind": "oracle",
+            "sample": f"{steps} steps from the initial load of the same workload, serial FP64 "
+                      f"oracle ({dt:.1f} s)"}
+
+
+def main() -> int:
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=2000)
+    ap.add_argument("--warmup", type=int, default=200)
+    ap.add_argument("--workload", default="column_20cm", choices=sorted(WORKLOADS))
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--cpu-steps", type=int, default=0, help="oracle sample length (0 = auto)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on exactly one GPU (no sharding or "
+                                   "collectives); run with --gpus 1"}))
+        return 2
+
+    import torch
+    from paper_2202_03215_amd.column import Column
+
+    cfg = WORKLOADS[args.workload]()
+    print(f"[bench] workload {args.workload}: init", file=sys.stderr, flush=True)
+    col = Column(cfg)
+    S = int(cfg["ion_subcycle"])
+    col.step(args.warmup)
+    col.sync()
+    c0 = col.counts()
+    print(f"[bench] warmup {args.warmup} done, n = {c0['n']}", file=sys.stderr, flush=True)
+    col.timer_enable(args.steps)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    col.step(args.steps)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    c1 = col.counts()
+    ker_ms, launches = col.timer_read()
+    col.timer_enable(0)
+    col.sync()
+    elapsed = t1 - t0
+    step0 = c0["step"]
+    ion_steps = sum(1 for k in range(step0, step0 + args.steps) if k % S == 0)
+    ne_avg = 0.5 * (c0["n"][0] + c1["n"][0])
+    ni_avg = 0.5 * (c0["n"][1] + c1["n"][1])
+    psteps = ne_avg * args.steps + ni_avg * ion_steps
+    value = psteps / elapsed
+
+    # roofline of the electron advance kernel
+    p_null = float(col.sizes.p_null)
+    bytes_per_launch = ne_avg * electron_bytes_per_step(p_null)
+    avg_s = ker_ms * 1e-3 / max(launches, 1)
+    achieved = bytes_per_launch / avg_s / 1e9
+    print(f"[bench] {args.steps} steps in {elapsed:.3f} s; advance kernel avg {avg_s * 1e6:.2f} us "
+          f"over {launches} launches", file=sys.stderr, flush=True)
+
+    out = {
+        "metric": "particle-steps/s at 1 GPU (plain FP64) + % HBM peak",
+        "value": value,
+        "unit": "particle-steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": elapsed * 1e3 / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": args.workload, "gas": cfg["gas"], "bc": cfg["bc"],
+                   "n_cells": cfg["n_cells"], "particles_per_cell": cfg["ppc"],
+                   "electrons": int(ne_avg), "ions": int(ni_avg), "dt": cfg["dt"],
+                   "ion_subcycle": S, "sort_interval": cfg["sort_interval"]},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "kernel": "k_advance<electron>", "avg_us": avg_s * 1e6,
+                     "bytes_per_launch": bytes_per_launch},
+    }
+    if not args.no_cpu:
+        steps = args.cpu_steps or max(5, int(4.0e8 / (c0["n"][0] + c0["n"][1] / S)))
+        print(f"[bench] cpu baseline: oracle, {steps} steps", file=sys.stderr, flush=True)
+        out["cpu_baseline"] = cpu_baseline(cfg, steps)
+    print(json.dumps(out), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

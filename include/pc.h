@@ -1,0 +1,192 @@
+/*
+ * pc.h -- C ABI of the MI355X (gfx950) 1D PIC-MCC positive-column library.
+ *
+ * The library advances a one-dimensional electrostatic Particle-In-Cell /
+ * Monte Carlo Collisions model of a neon or argon positive column: electrons
+ * and positive ions on a uniform grid, field from Poisson's equation every
+ * step, electron-atom elastic / lumped-excitation / ionization collisions and
+ * ion-atom charge exchange by the null-collision method, radial losses as a
+ * per-particle removal frequency (Boeuf, "Ionization waves (striations) in a
+ * low-current plasma column revisited with kinetic and fluid models",
+ * section II for the model, eq. (2) for the radial losses, section V for the
+ * bounded column).
+ *
+ * Conventions
+ *  - Every function returns a pc_status: PC_OK (0) or a negative error code.
+ *    No C++ exception crosses this boundary.  pc_last_error() returns a
+ *    thread-local human-readable detail for the last failure.
+ *  - Device memory is owned by the caller.  pc_init_column receives one
+ *    workspace of pc_sizes.workspace_bytes bytes (256-byte aligned) and lays
+ *    out all particle arrays, charges, fields and counters inside it; the
+ *    library never allocates device memory.  Output arrays are caller-owned
+ *    device buffers as documented per function.
+ *  - All work is enqueued on the caller's HIP stream (hipStream_t passed as
+ *    void*).  Functions marked "async" return before the work completes;
+ *    pc_sync / pc_get_counts wait for the stream and surface device-side
+ *    errors.  After a device-side error the handle is poisoned: further
+ *    pc_step calls return PC_ERR_POISONED until pc_set_state clears it.
+ *  - Particle state is structure-of-arrays, FP64: x [m] in [0, L), vx, vy,
+ *    vz [m/s] (vx is the leapfrog half-step velocity), id (uint32).  Node
+ *    arrays have pc_sizes.n_nodes entries: n_cells + 1 (bounded) or n_cells
+ *    (periodic).  Charges are int64 fixed point with 32 fractional bits: a
+ *    macroparticle contributes exactly 2^32 units split between its two
+ *    nodes.
+ */
+#ifndef PC_H
+#define PC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t pc_status;
+enum {
+    PC_OK = 0,
+    PC_ERR_INVALID_ARG = -1,     /* null pointer, bad size, bad enum */
+    PC_ERR_UNSTABLE_CONFIG = -2, /* violates dt < 0.2/w_pe, dx < lambda_De, nu_max dt <= 0.1 */
+    PC_ERR_CAPACITY = -3,        /* particle, birth or loss list capacity exceeded */
+    PC_ERR_NONFINITE = -4,       /* a position left [0, L) after the boundary rule, or NaN */
+    PC_ERR_ECAP = -5,            /* electron energy above eps_cap / frequency above nu_max */
+    PC_ERR_GCAP = -6,            /* ion-atom relative speed above g_cap */
+    PC_ERR_HIP = -7,             /* a HIP runtime call failed */
+    PC_ERR_POISONED = -8,        /* an earlier device-side error is pending */
+    PC_ERR_WORKSPACE = -9,       /* workspace too small or misaligned */
+    PC_ERR_IDS = -10             /* particle id space (2^32) exhausted */
+};
+
+enum { PC_BOUNDED = 0, PC_PERIODIC = 1 };
+enum { PC_WALL_OFF = 0, PC_WALL_FIXED = 1 };
+enum { PC_SHARE_OPB = 0, PC_SHARE_EQUAL = 1 };
+enum { PC_ELECTRON = 0, PC_ION = 1 };
+/* event codes written by pc_step into the optional per-id event buffers */
+enum { PC_EV_NONE = 0, PC_EV_ELASTIC = 1, PC_EV_EXCITE = 2, PC_EV_IONIZE = 3,
+       PC_EV_WALL = 4, PC_EV_ABSORB = 5, PC_EV_CX = 6, PC_EV_NULL = 7 };
+
+/* Column description (SI units unless noted).  Cross sections are the
+ * synthetic analytic forms: elastic A + B eps^p (p = +-1/2, eps in eV),
+ * excitation and ionization 4 smax (U/eps)(1 - U/eps) above threshold U [eV],
+ * constant charge exchange.  V is the anode potential (bounded) or E0 L
+ * (periodic, imposed mean field E = -E0 + E_sp, section II). */
+typedef struct pc_config {
+    int32_t bc, n_cells, ppc, ion_subcycle;
+    int32_t wall_mode, energy_sharing, poisson, sort_interval;
+    int32_t launch_blocks, pad0, pad1, pad2;  /* blocks of the particle kernels (0 = auto) */
+    double L, V, p_torr, Tg, n0, Te0_eV, Ti0_K, nu_w, dt, eps_cap, g_cap, capacity;
+    double M_amu, el_A, el_B, el_p, ex_U, ex_smax, iz_U, iz_smax, cx_sigma, opb_w;
+    uint64_t seed;
+} pc_config;
+
+typedef struct pc_sizes {
+    int64_t workspace_bytes; /* bytes the caller must provide */
+    int64_t capacity;        /* particle slots per species */
+    int64_t max_births;      /* ionizations per step */
+    int64_t max_losses;      /* losses per species per step */
+    int32_t n_nodes, n_cells;
+    double nu_max;           /* null-collision bound of the electrons [1/s] */
+    double p_null;           /* electron collision-candidate probability per step */
+    double p_cx;             /* ion candidate probability per ion step */
+} pc_sizes;
+
+typedef struct pc_counts {
+    int64_t n[2];            /* live particles per species */
+    int64_t next_id[2];      /* next id per species */
+    int64_t step;            /* index of the next step */
+    uint32_t errors;         /* sticky device error bits */
+    uint32_t pad;
+} pc_counts;
+
+typedef struct pc_column* pc_handle;
+
+/* Sizes of the workspace and lists for a config.  Validates the config. */
+pc_status pc_query_sizes(const pc_config* cfg, pc_sizes* out);
+
+/* Create a column in the caller's workspace and load it (async): uniform
+ * positions, Maxwellian velocities (electrons at Te0, ions at Ti0), ids
+ * 0..N0-1, deposit, field solve and the leapfrog half-step back of vx
+ * (section II: uniform and equal initial densities).  Rejects configs that
+ * break dt < 0.2/w_pe or dx < lambda_De (section II) or nu_max dt <= 0.1. */
+pc_status pc_init_column(const pc_config* cfg, void* workspace, size_t bytes,
+                         void* hip_stream, pc_handle* out);
+
+/* Advance n_steps full time steps (async).  Per step: electrons (CIC gather,
+ * leapfrog push, boundary, radial sink, null-collision MCC, fused fixed-point
+ * deposit), ions every ion_subcycle steps with dt_i = ion_subcycle dt,
+ * removal of losses, append of ionization products (ids by rank of the
+ * parent id), field solve; a per-cell counting sort every sort_interval
+ * steps (no effect on results). */
+pc_status pc_step(pc_handle h, int64_t n_steps);
+
+/* Deposit n positions (device FP64, all in [0, L)) with linear weighting
+ * into rho (device int64[n_nodes], overwritten).  Async. */
+pc_status pc_deposit(pc_handle h, const double* x, int64_t n, int64_t* rho);
+
+/* Solve Poisson's equation (section II) for node charges rho_e, rho_i (device
+ * int64[n_nodes]) into E (device double[n_nodes]) and, if phi is non-null,
+ * phi (device double[n_nodes]).  Bounded: phi(0) = 0, phi(L) = V.  Periodic:
+ * mean charge neutralised, phi(0) = 0, E = -E0 + E_sp.  Async. */
+pc_status pc_solve_field(pc_handle h, const int64_t* rho_e, const int64_t* rho_i,
+                         double* phi, double* E);
+
+/* Cell moments of the current state into out (device int64, async), layout
+ * with nc = n_cells: [0,nc) electron count, [nc,2nc) sum eps 2^20 (eV),
+ * [2nc,3nc) sum vx 2^10, [3nc,4nc) sum eps vx 2^4, [4nc,5nc) ion count,
+ * [5nc,6nc) ion sum vx 2^10, [6nc,7nc) ionizations since the last reset,
+ * then ceil(nc/cells_per_group) x 240 EEPF counts (0.25 eV bins on
+ * [0, 60) eV).  Each term is truncated to an integer per particle. */
+pc_status pc_moments(pc_handle h, int32_t cells_per_group, int32_t reset_iz, int64_t* out);
+
+/* Synchronise the stream and read the counters (blocking). */
+pc_status pc_get_counts(pc_handle h, pc_counts* out);
+
+/* Copy the first n live particles of a species into caller device arrays
+ * (any pointer may be null; cap = array length).  Async; n from pc_get_counts. */
+pc_status pc_get_state(pc_handle h, int32_t species, double* x, double* vx, double* vy,
+                       double* vz, uint32_t* id, int64_t cap);
+
+/* Replace a species' particles with n caller device arrays (async).  Clears
+ * a poisoned handle.  Positions must lie in [0, L). */
+pc_status pc_set_state(pc_handle h, int32_t species, int64_t n, const double* x,
+                       const double* vx, const double* vy, const double* vz,
+                       const uint32_t* id);
+
+/* Set the step index and next ids (blocking). */
+pc_status pc_set_counters(pc_handle h, int64_t step, int64_t next_e, int64_t next_i);
+
+/* Copy the current field E^n and the charges it was solved from (async;
+ * any pointer may be null). */
+pc_status pc_get_field(pc_handle h, double* E, int64_t* rho_e, int64_t* rho_i);
+/* Overwrite the current field E^n (async). */
+pc_status pc_set_field(pc_handle h, const double* E);
+
+/* Optional per-id event recording for parity checks: device uint8 buffers
+ * indexed by particle id; each step writes the event code of every particle
+ * it advances (ids >= len are skipped).  Null disables. */
+pc_status pc_set_events(pc_handle h, uint8_t* ev_e, int64_t len_e, uint8_t* ev_i,
+                        int64_t len_i);
+
+/* Kernel timer for roofline measurements: with max_launches > 0, pc_step
+ * brackets each launch of the electron advance kernel (the dominant kernel:
+ * gather, push, collisions, deposit) with a pair of HIP events on the
+ * column's stream, up to max_launches launches.  The event pool is created
+ * here, never inside pc_step; 0 disables the timer and frees the pool. */
+pc_status pc_timer_enable(pc_handle h, int64_t max_launches);
+/* Wait for the recorded launches and return their summed duration [ms] and
+ * count; resets the timer for the next window (blocking). */
+pc_status pc_timer_read(pc_handle h, double* total_ms, int64_t* launches);
+
+/* Synchronise the stream and map device error bits to a status. */
+pc_status pc_sync(pc_handle h);
+
+/* Free the host-side handle (the workspace stays with the caller). */
+void pc_destroy(pc_handle h);
+
+const char* pc_status_string(pc_status s);
+const char* pc_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,144 @@
+"""Python front-end of one PIC-MCC column on the GPU.
+
+PyTorch supplies device memory (one workspace tensor plus caller-side output
+tensors) and the HIP stream; the C ABI (include/pc.h) does the work.  Method
+names follow the C entry points: init_column (the constructor), step,
+deposit, solve_field, moments, get_state / set_state, get_field / set_field,
+set_counters, set_events, counts, sync.
+"""
+from __future__ import annotations
+
+import ctypes as C
+
+import torch
+
+from . import native as N
+
+
+def _ptr(t: torch.Tensor | None) -> int | None:
+    if t is None:
+        return None
+    if not t.is_cuda or not t.is_contiguous():
+        raise ValueError("expected a contiguous device tensor")
+    return t.data_ptr()
+
+
+class Column:
+    """A column created by pc_init_column in a torch-owned workspace."""
+
+    def __init__(self, cfg: dict, device: str | torch.device = "cuda:0",
+                 stream: torch.cuda.Stream | None = None):
+        self.cfg = dict(cfg)
+        self.device = torch.device(device)
+        self._c = N.make_config(cfg)
+        self.sizes = N.pc_sizes()
+        N.check(N.lib().pc_query_sizes(C.byref(self._c), C.byref(self.sizes)))
+        self.nn = int(self.sizes.n_nodes)
+        self.nc = int(self.sizes.n_cells)
+        self.capacity = int(self.sizes.capacity)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        with torch.cuda.device(self.device):
+            self.workspace = torch.empty(int(self.sizes.workspace_bytes), dtype=torch.uint8,
+                                         device=self.device)
+        h = C.c_void_p()
+        N.check(N.lib().pc_init_column(C.byref(self._c), self.workspace.data_ptr(),
+                                       int(self.sizes.workspace_bytes),
+                                       C.c_void_p(self.stream.cuda_stream), C.byref(h)))
+        self.h = h
+        self._events = None
+
+    def __del__(self):
+        h = getattr(self, "h", None)
+        if h is not None and h.value:
+            N.lib().pc_destroy(h)
+            self.h = None
+
+    # ------------------------------------------------------------ stepping
+    def step(self, n: int = 1) -> None:
+        N.check(N.lib().pc_step(self.h, int(n)))
+
+    def sync(self) -> None:
+        N.check(N.lib().pc_sync(self.h))
+
+    def counts(self) -> dict:
+        c = N.pc_counts()
+        N.check(N.lib().pc_get_counts(self.h, C.byref(c)))
+        return dict(n=(int(c.n[0]), int(c.n[1])), next_id=(int(c.next_id[0]), int(c.next_id[1])),
+                    step=int(c.step), errors=int(c.errors))
+
+    # ------------------------------------------------------ stand-alone ops
+    def _empty(self, n, dtype):
+        return torch.empty(n, dtype=dtype, device=self.device)
+
+    def deposit(self, x: torch.Tensor) -> torch.Tensor:
+        x = x.to(self.device, torch.float64).contiguous()
+        rho = self._empty(self.nn, torch.int64)
+        N.check(N.lib().pc_deposit(self.h, _ptr(x), x.numel(), _ptr(rho)))
+        return rho
+
+    def solve_field(self, rho_e: torch.Tensor, rho_i: torch.Tensor, want_phi: bool = True):
+        re = rho_e.to(self.device, torch.int64).contiguous()
+        ri = rho_i.to(self.device, torch.int64).contiguous()
+        E = self._empty(self.nn, torch.float64)
+        phi = self._empty(self.nn, torch.float64) if want_phi else None
+        N.check(N.lib().pc_solve_field(self.h, _ptr(re), _ptr(ri), _ptr(phi), _ptr(E)))
+        return phi, E
+
+    def moments(self, cells_per_group: int = 1, reset_iz: bool = False) -> torch.Tensor:
+        ng = (self.nc + cells_per_group - 1) // cells_per_group
+        out = self._empty(7 * self.nc + ng * 240, torch.int64)
+        N.check(N.lib().pc_moments(self.h, int(cells_per_group), int(reset_iz), _ptr(out)))
+        return out
+
+    # ------------------------------------------------------------ state I/O
+    def get_state(self, species: int):
+        n = self.counts()["n"][species]
+        x, vx, vy, vz = (self._empty(n, torch.float64) for _ in range(4))
+        ids = self._empty(n, torch.int32)
+        N.check(N.lib().pc_get_state(self.h, int(species), _ptr(x), _ptr(vx), _ptr(vy), _ptr(vz),
+                                     _ptr(ids), n))
+        return x, vx, vy, vz, ids
+
+    def set_state(self, species: int, x, vx, vy, vz, ids) -> None:
+        ts = [torch.as_tensor(a).to(self.device, torch.float64).contiguous() for a in (x, vx, vy, vz)]
+        it = torch.as_tensor(ids).to(torch.int64).to(torch.int32).to(self.device).contiguous()
+        N.check(N.lib().pc_set_state(self.h, int(species), it.numel(), *[_ptr(t) for t in ts],
+                                     _ptr(it)))
+        torch.cuda.synchronize(self.device)
+
+    def set_counters(self, step: int, next_e: int, next_i: int) -> None:
+        N.check(N.lib().pc_set_counters(self.h, int(step), int(next_e), int(next_i)))
+
+    def get_field(self):
+        E = self._empty(self.nn, torch.float64)
+        re = self._empty(self.nn, torch.int64)
+        ri = self._empty(self.nn, torch.int64)
+        N.check(N.lib().pc_get_field(self.h, _ptr(E), _ptr(re), _ptr(ri)))
+        return E, re, ri
+
+    def set_field(self, E) -> None:
+        e = torch.as_tensor(E).to(self.device, torch.float64).contiguous()
+        N.check(N.lib().pc_set_field(self.h, _ptr(e)))
+        torch.cuda.synchronize(self.device)
+
+    def set_events(self, len_e: int, len_i: int):
+        """Allocate per-id event buffers (uint8) that each step fills."""
+        ev_e = torch.zeros(len_e, dtype=torch.uint8, device=self.device)
+        ev_i = torch.zeros(len_i, dtype=torch.uint8, device=self.device)
+        N.check(N.lib().pc_set_events(self.h, _ptr(ev_e), len_e, _ptr(ev_i), len_i))
+        self._events = (ev_e, ev_i)
+        return self._events
+
+    def timer_enable(self, max_launches: int) -> None:
+        N.check(N.lib().pc_timer_enable(self.h, int(max_launches)))
+
+    def timer_read(self):
+        """(summed duration in ms, launches) of the timed electron-advance launches."""
+        ms = C.c_double()
+        n = C.c_int64()
+        N.check(N.lib().pc_timer_read(self.h, C.byref(ms), C.byref(n)))
+        return float(ms.value), int(n.value)
+
+    def clear_events(self) -> None:
+        N.check(N.lib().pc_set_events(self.h, None, 0, None, 0))
+        self._events = None

@@ -1,0 +1,631 @@
+// api.hip -- host implementation of the C ABI declared in include/pc.h.
+//
+// The handle owns host metadata only; every device byte lives in the
+// caller's workspace.  Derived constants follow the model of section II of
+// the paper (Boeuf): gas density from p and T_g, leapfrog charge-to-mass
+// factors, the null-collision bound over [0, eps_cap], the per-step removal
+// probability of the radial sink (eq. (2) frequency), the Gauss's-law field
+// jump per fixed-point charge unit.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/pc.h"
+#include "device.h"
+#include "launch.h"
+
+using pcdev::Counters;
+using pcdev::Params;
+using pcdev::Soa;
+
+namespace {
+
+// CODATA 2018
+constexpr double kQe = 1.602176634e-19;
+constexpr double kMe = 9.1093837015e-31;
+constexpr double kAmu = 1.66053906660e-27;
+constexpr double kKb = 1.380649e-23;
+constexpr double kEps0 = 8.8541878128e-12;
+const double kTorr = 101325.0 / 760.0;
+
+thread_local std::string g_last_error;
+
+pc_status fail(pc_status s, const std::string& msg)
+{
+    g_last_error = msg;
+    return s;
+}
+
+pc_status hip_fail(hipError_t e, const char* where)
+{
+    return fail(PC_ERR_HIP, std::string(where) + ": " + hipGetErrorString(e));
+}
+
+#define HIPCHK(call)                                   \
+    do {                                               \
+        hipError_t e_ = (call);                        \
+        if (e_ != hipSuccess) return hip_fail(e_, #call); \
+    } while (0)
+
+int64_t align256(int64_t v) { return (v + 255) & ~int64_t(255); }
+
+struct Derived {
+    int nc, nn, periodic;
+    double dx, inv_dx, dti, Ng, M, c_eps, qmdt_e, qmdt_i, W, fpc, E0;
+    double sig_a, sig_e0, sig_i0, mr2, sx4, si4;
+    double nu_max, P_null, T_we, T_wi, P_cx;
+    int64_t n0, cap, max_births, max_holes;
+};
+
+double sig_el_host(const pc_config& c, double eps)
+{
+    if (c.el_p > 0.0) return c.el_A + c.el_B * std::sqrt(eps);
+    return eps > 0.0 ? c.el_A + c.el_B / std::sqrt(eps) : c.el_A;
+}
+
+double sig_in_host(double eps, double U, double s4)
+{
+    if (eps > U) {
+        const double t = U / eps;
+        return s4 * t * (1.0 - t);
+    }
+    return 0.0;
+}
+
+pc_status derive(const pc_config* c, Derived* d)
+{
+    if (!c || !d) return fail(PC_ERR_INVALID_ARG, "null config");
+    if (c->bc != PC_BOUNDED && c->bc != PC_PERIODIC) return fail(PC_ERR_INVALID_ARG, "bc");
+    if (c->n_cells < 2) return fail(PC_ERR_INVALID_ARG, "n_cells < 2");
+    if (!(c->L > 0.0) || !(c->dt > 0.0) || c->ppc < 1 || c->ion_subcycle < 1)
+        return fail(PC_ERR_INVALID_ARG, "L, dt, ppc and ion_subcycle must be positive");
+    if (c->el_p != 0.5 && c->el_p != -0.5) return fail(PC_ERR_INVALID_ARG, "el_p must be +0.5 or -0.5");
+    if (c->wall_mode != PC_WALL_OFF && c->wall_mode != PC_WALL_FIXED) return fail(PC_ERR_INVALID_ARG, "wall_mode");
+    if (c->energy_sharing != PC_SHARE_OPB && c->energy_sharing != PC_SHARE_EQUAL)
+        return fail(PC_ERR_INVALID_ARG, "energy_sharing");
+    if (!(c->eps_cap > 0.0) || !(c->g_cap > 0.0) || !(c->M_amu > 0.0) || !(c->n0 > 0.0) || !(c->Tg > 0.0))
+        return fail(PC_ERR_INVALID_ARG, "eps_cap, g_cap, M_amu, n0, Tg must be positive");
+    if (c->sort_interval < 0) return fail(PC_ERR_INVALID_ARG, "sort_interval < 0");
+    if (c->launch_blocks < 0 || c->launch_blocks > 65536) return fail(PC_ERR_INVALID_ARG, "launch_blocks");
+    d->nc = c->n_cells;
+    d->periodic = c->bc == PC_PERIODIC;
+    d->nn = d->periodic ? d->nc : d->nc + 1;
+    if (d->nn > pclaunch::max_nodes()) return fail(PC_ERR_INVALID_ARG, "too many nodes for the field solve");
+    d->dx = c->L / double(d->nc);
+    d->inv_dx = double(d->nc) / c->L;
+    d->dti = double(c->ion_subcycle) * c->dt;
+    d->Ng = c->p_torr * kTorr / (kKb * c->Tg);
+    d->M = c->M_amu * kAmu;
+    d->c_eps = 0.5 * kMe / kQe;
+    d->qmdt_e = (-kQe * c->dt) / kMe;
+    d->qmdt_i = (kQe * d->dti) / d->M;
+    d->W = c->n0 * d->dx / double(c->ppc);
+    d->fpc = kQe * d->W / pcdev::kUnitD / kEps0;
+    d->E0 = c->V / c->L;
+    d->sig_a = std::sqrt(kKb * c->Tg / d->M);
+    d->sig_e0 = std::sqrt(c->Te0_eV * kQe / kMe);
+    d->sig_i0 = std::sqrt(kKb * c->Ti0_K / d->M);
+    d->mr2 = 2.0 * kMe / d->M;
+    d->sx4 = 4.0 * c->ex_smax;
+    d->si4 = 4.0 * c->iz_smax;
+    // null-collision bound: largest Ng sigma_tot v on a 65536-interval grid of
+    // [0, eps_cap], with a 0.1 % margin
+    {
+        const int G = 65536;
+        double mx = 0.0;
+        for (int k = 0; k <= G; ++k) {
+            const double eps = c->eps_cap * double(k) / double(G);
+            const double v = std::sqrt(eps / d->c_eps);
+            const double s = sig_el_host(*c, eps) + sig_in_host(eps, c->ex_U, d->sx4) +
+                             sig_in_host(eps, c->iz_U, d->si4);
+            const double nu = s * v * d->Ng;
+            if (nu > mx) mx = nu;
+        }
+        d->nu_max = mx * 1.001;
+    }
+    d->P_null = 1.0 - std::exp(-d->nu_max * c->dt);
+    if (c->wall_mode == PC_WALL_FIXED) {
+        d->T_we = std::exp(-c->nu_w * c->dt);
+        d->T_wi = std::exp(-c->nu_w * d->dti);
+    } else {
+        d->T_we = 2.0;
+        d->T_wi = 2.0;
+    }
+    d->P_cx = 1.0 - std::exp(-d->Ng * c->cx_sigma * c->g_cap * d->dti);
+    // stability (section II): dt < 0.2 / w_pe and dx < lambda_De; collision
+    // probabilities per step small enough for one collision per step
+    const double wpe = std::sqrt(c->n0 * kQe * kQe / (kEps0 * kMe));
+    if (!(c->dt < 0.2 / wpe))
+        return fail(PC_ERR_UNSTABLE_CONFIG, "dt must be below 0.2/w_pe");
+    if (c->Te0_eV > 0.0) {
+        const double lde = std::sqrt(kEps0 * c->Te0_eV / (c->n0 * kQe));
+        if (!(d->dx < lde)) return fail(PC_ERR_UNSTABLE_CONFIG, "dx must be below the Debye length");
+    }
+    if (!(d->nu_max * c->dt <= 0.1)) return fail(PC_ERR_UNSTABLE_CONFIG, "nu_max dt above 0.1");
+    if (!(d->Ng * c->cx_sigma * c->g_cap * d->dti <= 0.1))
+        return fail(PC_ERR_UNSTABLE_CONFIG, "ion null-collision probability above 0.1");
+    d->n0 = int64_t(c->ppc) * d->nc;
+    const double capf = c->capacity > 1.0 ? c->capacity : 1.0;
+    int64_t cap = int64_t(std::ceil(double(d->n0) * capf));
+    cap = std::max<int64_t>(1024, (cap + 255) & ~int64_t(255));
+    if (cap >= (int64_t(1) << 31)) return fail(PC_ERR_INVALID_ARG, "capacity above 2^31 particles");
+    d->cap = cap;
+    d->max_births = std::max<int64_t>(4096, cap / 256);
+    d->max_holes = std::max<int64_t>(8192, cap / 64);
+    return PC_OK;
+}
+
+struct Layout {
+    int64_t counters, soa[2][2][5], rho[2][2], E, births, holes[2], lists, bitmap, iz, sort_cnt, sort_off, total;
+};
+
+Layout layout(const Derived& d)
+{
+    Layout L{};
+    int64_t o = 0;
+    auto take = [&](int64_t bytes) {
+        const int64_t at = o;
+        o = align256(o + bytes);
+        return at;
+    };
+    L.counters = take(sizeof(Counters));
+    for (int s = 0; s < 2; ++s)
+        for (int b = 0; b < 2; ++b) {
+            for (int f = 0; f < 4; ++f) L.soa[s][b][f] = take(d.cap * 8);
+            L.soa[s][b][4] = take(d.cap * 4);
+        }
+    for (int s = 0; s < 2; ++s)
+        for (int b = 0; b < 2; ++b) L.rho[s][b] = take(int64_t(d.nn) * 8);
+    L.E = take(int64_t(d.nn + 1) * 8);
+    L.births = take(d.max_births * int64_t(sizeof(pcdev::Birth)));
+    L.holes[0] = take(d.max_holes * 4);
+    L.holes[1] = take(d.max_holes * 4);
+    L.lists = take(2 * d.max_holes * 4);
+    L.bitmap = take((d.max_holes / 32 + 1) * 4);
+    L.iz = take(int64_t(d.nc) * 8);
+    L.sort_cnt = take(int64_t(d.nc) * 4);
+    L.sort_off = take(int64_t(d.nc) * 4);
+    L.total = o;
+    return L;
+}
+
+}  // namespace
+
+struct pc_column {
+    pc_config cfg;
+    Derived d;
+    Params P;
+    hipStream_t st;
+    Soa buf[2][2];
+    int cur[2];
+    int64_t* rho[2][2];
+    int re_cur, ri_cur;
+    int64_t step;
+    int poisoned;
+    uint8_t* ev[2];
+    int64_t evlen[2];
+    int grid;
+    Counters host_cnt;
+    std::vector<hipEvent_t> tev;   // timer pool: 2 events per launch
+    int64_t tcount;
+};
+
+namespace {
+
+pc_status map_errors(uint32_t e)
+{
+    if (e == 0) return PC_OK;
+    if (e & (pcdev::kErrRange | pcdev::kErrField)) return fail(PC_ERR_NONFINITE, "position or field out of range");
+    if (e & (pcdev::kErrBirths | pcdev::kErrLosses | pcdev::kErrCapacity))
+        return fail(PC_ERR_CAPACITY, "birth, loss or particle capacity exceeded");
+    if (e & (pcdev::kErrECap | pcdev::kErrNuMax)) return fail(PC_ERR_ECAP, "electron energy above eps_cap");
+    if (e & pcdev::kErrGCap) return fail(PC_ERR_GCAP, "ion-atom relative speed above g_cap");
+    if (e & pcdev::kErrIds) return fail(PC_ERR_IDS, "id space exhausted");
+    return fail(PC_ERR_HIP, "unknown device error");
+}
+
+pc_status read_counters(pc_column* h)
+{
+    HIPCHK(hipMemcpyAsync(&h->host_cnt, h->P.cnt, sizeof(Counters), hipMemcpyDeviceToHost, h->st));
+    HIPCHK(hipStreamSynchronize(h->st));
+    return PC_OK;
+}
+
+pc_status write_counters(pc_column* h)
+{
+    HIPCHK(hipMemcpyAsync(h->P.cnt, &h->host_cnt, sizeof(Counters), hipMemcpyHostToDevice, h->st));
+    HIPCHK(hipStreamSynchronize(h->st));
+    return PC_OK;
+}
+
+Soa soa_of(const pc_column* h, int s) { return h->buf[s][h->cur[s]]; }
+
+pc_status run_sort(pc_column* h)
+{
+    for (int s = 0; s < 2; ++s) {
+        const Soa src = h->buf[s][h->cur[s]];
+        const Soa dst = h->buf[s][1 - h->cur[s]];
+        HIPCHK(pclaunch::sort(h->P, s, src, dst, h->grid, h->st));
+        h->cur[s] = 1 - h->cur[s];
+    }
+    return PC_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+pc_status pc_query_sizes(const pc_config* cfg, pc_sizes* out)
+{
+    if (!out) return fail(PC_ERR_INVALID_ARG, "null output");
+    Derived d;
+    const pc_status s = derive(cfg, &d);
+    if (s != PC_OK) return s;
+    const Layout L = layout(d);
+    out->workspace_bytes = L.total;
+    out->capacity = d.cap;
+    out->max_births = d.max_births;
+    out->max_losses = d.max_holes;
+    out->n_nodes = d.nn;
+    out->n_cells = d.nc;
+    out->nu_max = d.nu_max;
+    out->p_null = d.P_null;
+    out->p_cx = d.P_cx;
+    return PC_OK;
+}
+
+pc_status pc_init_column(const pc_config* cfg, void* workspace, size_t bytes, void* hip_stream, pc_handle* out)
+{
+    if (!out || !workspace) return fail(PC_ERR_INVALID_ARG, "null workspace or handle");
+    *out = nullptr;
+    Derived d;
+    pc_status s = derive(cfg, &d);
+    if (s != PC_OK) return s;
+    const Layout L = layout(d);
+    if (int64_t(bytes) < L.total) return fail(PC_ERR_WORKSPACE, "workspace too small");
+    if (reinterpret_cast<uintptr_t>(workspace) & 255u) return fail(PC_ERR_WORKSPACE, "workspace not 256-byte aligned");
+    pc_column* h = new (std::nothrow) pc_column();
+    if (!h) return fail(PC_ERR_INVALID_ARG, "host allocation failed");
+    h->cfg = *cfg;
+    h->d = d;
+    h->st = static_cast<hipStream_t>(hip_stream);
+    char* base = static_cast<char*>(workspace);
+    for (int sp = 0; sp < 2; ++sp)
+        for (int b = 0; b < 2; ++b) {
+            Soa& q = h->buf[sp][b];
+            q.x = reinterpret_cast<double*>(base + L.soa[sp][b][0]);
+            q.vx = reinterpret_cast<double*>(base + L.soa[sp][b][1]);
+            q.vy = reinterpret_cast<double*>(base + L.soa[sp][b][2]);
+            q.vz = reinterpret_cast<double*>(base + L.soa[sp][b][3]);
+            q.id = reinterpret_cast<uint32_t*>(base + L.soa[sp][b][4]);
+            h->rho[sp][b] = reinterpret_cast<int64_t*>(base + L.rho[sp][b]);
+        }
+    Params& P = h->P;
+    P.nc = d.nc;
+    P.nn = d.nn;
+    P.periodic = d.periodic;
+    P.ion_subcycle = cfg->ion_subcycle;
+    P.L = cfg->L;
+    P.dx = d.dx;
+    P.inv_dx = d.inv_dx;
+    P.dt = cfg->dt;
+    P.dti = d.dti;
+    P.qmdt_e = d.qmdt_e;
+    P.qmdt_i = d.qmdt_i;
+    P.c_eps = d.c_eps;
+    P.sig_a = d.sig_a;
+    P.Ng = d.Ng;
+    P.nu_max = d.nu_max;
+    P.P_null = d.P_null;
+    P.T_we = d.T_we;
+    P.T_wi = d.T_wi;
+    P.P_cx = d.P_cx;
+    P.g_cap = cfg->g_cap;
+    P.eps_cap = cfg->eps_cap;
+    P.mr2 = d.mr2;
+    P.el_A = cfg->el_A;
+    P.el_B = cfg->el_B;
+    P.ex_U = cfg->ex_U;
+    P.sx4 = d.sx4;
+    P.iz_U = cfg->iz_U;
+    P.si4 = d.si4;
+    P.opb_w = cfg->opb_w;
+    P.el_pos = cfg->el_p > 0.0;
+    P.share_equal = cfg->energy_sharing == PC_SHARE_EQUAL;
+    P.poisson = cfg->poisson != 0;
+    P.fpc = d.fpc;
+    P.E0 = d.E0;
+    P.V = cfg->V;
+    P.key0 = uint32_t(cfg->seed);
+    P.key1 = uint32_t(cfg->seed >> 32);
+    P.cap = d.cap;
+    P.max_births = d.max_births;
+    P.max_holes = d.max_holes;
+    P.cnt = reinterpret_cast<Counters*>(base + L.counters);
+    P.births = reinterpret_cast<pcdev::Birth*>(base + L.births);
+    P.holes[0] = reinterpret_cast<uint32_t*>(base + L.holes[0]);
+    P.holes[1] = reinterpret_cast<uint32_t*>(base + L.holes[1]);
+    P.lists = reinterpret_cast<uint32_t*>(base + L.lists);
+    P.bitmap = reinterpret_cast<uint32_t*>(base + L.bitmap);
+    P.iz = reinterpret_cast<int64_t*>(base + L.iz);
+    P.E = reinterpret_cast<double*>(base + L.E);
+    P.sort_cnt = reinterpret_cast<int32_t*>(base + L.sort_cnt);
+    P.sort_off = reinterpret_cast<int32_t*>(base + L.sort_off);
+    h->grid = cfg->launch_blocks > 0 ? cfg->launch_blocks
+                                     : int(std::min<int64_t>(4096, std::max<int64_t>(1, (d.cap + 255) / 256)));
+    h->cur[0] = h->cur[1] = 0;
+    h->re_cur = h->ri_cur = 0;
+    h->step = 0;
+
+    auto cleanup = [&](pc_status st) {
+        delete h;
+        return st;
+    };
+    std::memset(&h->host_cnt, 0, sizeof(Counters));
+    h->host_cnt.n[0] = h->host_cnt.n[1] = d.n0;
+    h->host_cnt.next_id[0] = h->host_cnt.next_id[1] = d.n0;
+    if ((s = write_counters(h)) != PC_OK) return cleanup(s);
+    hipError_t e = hipSuccess;
+    for (int sp = 0; sp < 2 && e == hipSuccess; ++sp)
+        for (int b = 0; b < 2 && e == hipSuccess; ++b) e = pclaunch::fill_i64(h->rho[sp][b], d.nn, 0, h->st);
+    if (e == hipSuccess) e = pclaunch::fill_i64(P.iz, d.nc, 0, h->st);
+    if (e == hipSuccess) e = pclaunch::fill_i64(reinterpret_cast<int64_t*>(P.sort_cnt), (d.nc + 1) / 2, 0, h->st);
+    if (e == hipSuccess) e = pclaunch::load(P, 0, h->buf[0][0], d.n0, d.sig_e0, h->st);
+    if (e == hipSuccess) e = pclaunch::load(P, 1, h->buf[1][0], d.n0, d.sig_i0, h->st);
+    if (e == hipSuccess) e = pclaunch::deposit(P, h->buf[0][0].x, d.n0, h->rho[0][0], h->st);
+    if (e == hipSuccess) e = pclaunch::deposit(P, h->buf[1][0].x, d.n0, h->rho[1][0], h->st);
+    if (e == hipSuccess) e = pclaunch::field(P, h->rho[0][0], h->rho[1][0], P.E, nullptr, 1, h->st);
+    if (e == hipSuccess) e = pclaunch::halfstep(P, h->buf[0][0], d.n0, 0.5 * d.qmdt_e, h->st);
+    if (e == hipSuccess) e = pclaunch::halfstep(P, h->buf[1][0], d.n0, 0.5 * d.qmdt_i, h->st);
+    if (e != hipSuccess) return cleanup(hip_fail(e, "pc_init_column launch"));
+    if (cfg->sort_interval > 0 && (s = run_sort(h)) != PC_OK) return cleanup(s);
+    if ((s = read_counters(h)) != PC_OK) return cleanup(s);
+    if (h->host_cnt.err) return cleanup(map_errors(h->host_cnt.err));
+    *out = h;
+    return PC_OK;
+}
+
+pc_status pc_step(pc_handle h, int64_t n_steps)
+{
+    if (!h || n_steps < 0) return fail(PC_ERR_INVALID_ARG, "bad handle or step count");
+    if (h->poisoned) return fail(PC_ERR_POISONED, "an earlier device error is pending");
+    const int S = h->cfg.ion_subcycle;
+    const int K = h->cfg.sort_interval;
+    for (int64_t k = 0; k < n_steps; ++k) {
+        const bool ion = h->step % S == 0;
+        int64_t* re_new = h->rho[0][1 - h->re_cur];
+        int64_t* re_old = h->rho[0][h->re_cur];
+        int64_t* ri_use = ion ? h->rho[1][1 - h->ri_cur] : h->rho[1][h->ri_cur];
+        int64_t* ri_old = ion ? h->rho[1][h->ri_cur] : nullptr;
+        const Soa se = soa_of(h, 0), si = soa_of(h, 1);
+        const bool timed = h->tcount < int64_t(h->tev.size() / 2);
+        if (timed) HIPCHK(hipEventRecord(h->tev[2 * h->tcount], h->st));
+        HIPCHK(pclaunch::advance(h->P, 0, se, re_new, h->ev[0], h->evlen[0], h->grid, h->st));
+        if (timed) {
+            HIPCHK(hipEventRecord(h->tev[2 * h->tcount + 1], h->st));
+            h->tcount += 1;
+        }
+        if (ion) HIPCHK(pclaunch::advance(h->P, 1, si, ri_use, h->ev[1], h->evlen[1], h->grid, h->st));
+        HIPCHK(pclaunch::finish(h->P, se, si, re_new, ri_use, re_old, ri_old, h->st));
+        h->re_cur = 1 - h->re_cur;
+        if (ion) h->ri_cur = 1 - h->ri_cur;
+        h->step += 1;
+        if (K > 0 && h->step % K == 0) {
+            const pc_status s = run_sort(h);
+            if (s != PC_OK) return s;
+        }
+    }
+    return PC_OK;
+}
+
+pc_status pc_deposit(pc_handle h, const double* x, int64_t n, int64_t* rho)
+{
+    if (!h || !rho || n < 0 || (n > 0 && !x)) return fail(PC_ERR_INVALID_ARG, "bad deposit arguments");
+    HIPCHK(pclaunch::deposit(h->P, x, n, rho, h->st));
+    return PC_OK;
+}
+
+pc_status pc_solve_field(pc_handle h, const int64_t* rho_e, const int64_t* rho_i, double* phi, double* E)
+{
+    if (!h || !rho_e || !rho_i || !E) return fail(PC_ERR_INVALID_ARG, "bad field arguments");
+    HIPCHK(pclaunch::field(h->P, rho_e, rho_i, E, phi, 0, h->st));
+    return PC_OK;
+}
+
+pc_status pc_moments(pc_handle h, int32_t cells_per_group, int32_t reset_iz, int64_t* out)
+{
+    if (!h || !out || cells_per_group < 1) return fail(PC_ERR_INVALID_ARG, "bad moments arguments");
+    const int64_t ng = (h->d.nc + cells_per_group - 1) / cells_per_group;
+    const int64_t len = 7 * int64_t(h->d.nc) + ng * 240;
+    HIPCHK(pclaunch::moments(h->P, soa_of(h, 0), soa_of(h, 1), cells_per_group, reset_iz, out, len, h->st));
+    return PC_OK;
+}
+
+pc_status pc_get_counts(pc_handle h, pc_counts* out)
+{
+    if (!h || !out) return fail(PC_ERR_INVALID_ARG, "null argument");
+    const pc_status s = read_counters(h);
+    if (s != PC_OK) return s;
+    for (int k = 0; k < 2; ++k) {
+        out->n[k] = h->host_cnt.n[k];
+        out->next_id[k] = h->host_cnt.next_id[k];
+    }
+    out->step = h->host_cnt.step;
+    out->errors = h->host_cnt.err;
+    out->pad = 0;
+    return PC_OK;
+}
+
+pc_status pc_get_state(pc_handle h, int32_t species, double* x, double* vx, double* vy, double* vz, uint32_t* id,
+                       int64_t cap)
+{
+    if (!h || (species != 0 && species != 1) || cap < 0) return fail(PC_ERR_INVALID_ARG, "bad state arguments");
+    pc_status s = read_counters(h);
+    if (s != PC_OK) return s;
+    const int64_t n = std::min<int64_t>(cap, h->host_cnt.n[species]);
+    const Soa q = soa_of(h, species);
+    if (n == 0) return PC_OK;
+    if (x) HIPCHK(hipMemcpyAsync(x, q.x, n * 8, hipMemcpyDeviceToDevice, h->st));
+    if (vx) HIPCHK(hipMemcpyAsync(vx, q.vx, n * 8, hipMemcpyDeviceToDevice, h->st));
+    if (vy) HIPCHK(hipMemcpyAsync(vy, q.vy, n * 8, hipMemcpyDeviceToDevice, h->st));
+    if (vz) HIPCHK(hipMemcpyAsync(vz, q.vz, n * 8, hipMemcpyDeviceToDevice, h->st));
+    if (id) HIPCHK(hipMemcpyAsync(id, q.id, n * 4, hipMemcpyDeviceToDevice, h->st));
+    return PC_OK;
+}
+
+pc_status pc_set_state(pc_handle h, int32_t species, int64_t n, const double* x, const double* vx,
+                       const double* vy, const double* vz, const uint32_t* id)
+{
+    if (!h || (species != 0 && species != 1) || n < 0) return fail(PC_ERR_INVALID_ARG, "bad state arguments");
+    if (n > h->d.cap) return fail(PC_ERR_CAPACITY, "state larger than the particle capacity");
+    if (n > 0 && (!x || !vx || !vy || !vz || !id)) return fail(PC_ERR_INVALID_ARG, "null state array");
+    pc_status s = read_counters(h);
+    if (s != PC_OK) return s;
+    const Soa q = soa_of(h, species);
+    if (n > 0) {
+        HIPCHK(hipMemcpyAsync(q.x, x, n * 8, hipMemcpyDeviceToDevice, h->st));
+        HIPCHK(hipMemcpyAsync(q.vx, vx, n * 8, hipMemcpyDeviceToDevice, h->st));
+        HIPCHK(hipMemcpyAsync(q.vy, vy, n * 8, hipMemcpyDeviceToDevice, h->st));
+        HIPCHK(hipMemcpyAsync(q.vz, vz, n * 8, hipMemcpyDeviceToDevice, h->st));
+        HIPCHK(hipMemcpyAsync(q.id, id, n * 4, hipMemcpyDeviceToDevice, h->st));
+    }
+    h->host_cnt.n[species] = n;
+    h->host_cnt.err = 0;
+    h->host_cnt.nb = 0;
+    h->host_cnt.nh[0] = h->host_cnt.nh[1] = 0;
+    if ((s = write_counters(h)) != PC_OK) return s;
+    // positions must lie in [0, L): checked by a deposit into scratch charge
+    if (n > 0) {
+        int64_t* scratch = h->rho[0][1 - h->re_cur];   // the next electron charge buffer: zero and unused
+        HIPCHK(pclaunch::deposit(h->P, q.x, n, scratch, h->st));
+        HIPCHK(pclaunch::fill_i64(scratch, h->d.nn, 0, h->st));
+        if ((s = read_counters(h)) != PC_OK) return s;
+        if (h->host_cnt.err) {
+            h->poisoned = 1;
+            return map_errors(h->host_cnt.err);
+        }
+    }
+    h->poisoned = 0;
+    return PC_OK;
+}
+
+pc_status pc_set_counters(pc_handle h, int64_t step, int64_t next_e, int64_t next_i)
+{
+    if (!h || step < 0 || next_e < 0 || next_i < 0 || step > 0xFFFFFFFFll || next_e > 0xFFFFFFFFll ||
+        next_i > 0xFFFFFFFFll)
+        return fail(PC_ERR_INVALID_ARG, "bad counters");
+    pc_status s = read_counters(h);
+    if (s != PC_OK) return s;
+    h->host_cnt.step = step;
+    h->host_cnt.next_id[0] = next_e;
+    h->host_cnt.next_id[1] = next_i;
+    if ((s = write_counters(h)) != PC_OK) return s;
+    h->step = step;
+    return PC_OK;
+}
+
+pc_status pc_get_field(pc_handle h, double* E, int64_t* rho_e, int64_t* rho_i)
+{
+    if (!h) return fail(PC_ERR_INVALID_ARG, "null handle");
+    const int64_t nb = int64_t(h->d.nn) * 8;
+    if (E) HIPCHK(hipMemcpyAsync(E, h->P.E, nb, hipMemcpyDeviceToDevice, h->st));
+    if (rho_e) HIPCHK(hipMemcpyAsync(rho_e, h->rho[0][h->re_cur], nb, hipMemcpyDeviceToDevice, h->st));
+    if (rho_i) HIPCHK(hipMemcpyAsync(rho_i, h->rho[1][h->ri_cur], nb, hipMemcpyDeviceToDevice, h->st));
+    return PC_OK;
+}
+
+pc_status pc_set_field(pc_handle h, const double* E)
+{
+    if (!h || !E) return fail(PC_ERR_INVALID_ARG, "null argument");
+    HIPCHK(hipMemcpyAsync(h->P.E, E, int64_t(h->d.nn) * 8, hipMemcpyDeviceToDevice, h->st));
+    if (h->d.periodic) HIPCHK(hipMemcpyAsync(h->P.E + h->d.nc, E, 8, hipMemcpyDeviceToDevice, h->st));
+    return PC_OK;
+}
+
+pc_status pc_set_events(pc_handle h, uint8_t* ev_e, int64_t len_e, uint8_t* ev_i, int64_t len_i)
+{
+    if (!h || len_e < 0 || len_i < 0) return fail(PC_ERR_INVALID_ARG, "bad event buffers");
+    h->ev[0] = ev_e;
+    h->evlen[0] = ev_e ? len_e : 0;
+    h->ev[1] = ev_i;
+    h->evlen[1] = ev_i ? len_i : 0;
+    return PC_OK;
+}
+
+pc_status pc_sync(pc_handle h)
+{
+    if (!h) return fail(PC_ERR_INVALID_ARG, "null handle");
+    const pc_status s = read_counters(h);
+    if (s != PC_OK) return s;
+    if (h->host_cnt.err) {
+        h->poisoned = 1;
+        return map_errors(h->host_cnt.err);
+    }
+    return PC_OK;
+}
+
+pc_status pc_timer_enable(pc_handle h, int64_t max_launches)
+{
+    if (!h || max_launches < 0 || max_launches > (int64_t(1) << 24)) return fail(PC_ERR_INVALID_ARG, "bad timer size");
+    HIPCHK(hipStreamSynchronize(h->st));
+    for (hipEvent_t e : h->tev) HIPCHK(hipEventDestroy(e));
+    h->tev.clear();
+    h->tcount = 0;
+    for (int64_t k = 0; k < 2 * max_launches; ++k) {
+        hipEvent_t e;
+        HIPCHK(hipEventCreate(&e));
+        h->tev.push_back(e);
+    }
+    return PC_OK;
+}
+
+pc_status pc_timer_read(pc_handle h, double* total_ms, int64_t* launches)
+{
+    if (!h || !total_ms || !launches) return fail(PC_ERR_INVALID_ARG, "null argument");
+    HIPCHK(hipStreamSynchronize(h->st));
+    double tot = 0.0;
+    for (int64_t k = 0; k < h->tcount; ++k) {
+        float ms = 0.0f;
+        HIPCHK(hipEventElapsedTime(&ms, h->tev[2 * k], h->tev[2 * k + 1]));
+        tot += double(ms);
+    }
+    *total_ms = tot;
+    *launches = h->tcount;
+    h->tcount = 0;
+    return PC_OK;
+}
+
+void pc_destroy(pc_handle h)
+{
+    if (!h) return;
+    for (hipEvent_t e : h->tev) (void)hipEventDestroy(e);
+    delete h;
+}
+
+const char* pc_status_string(pc_status s)
+{
+    switch (s) {
+    case PC_OK: return "ok";
+    case PC_ERR_INVALID_ARG: return "invalid argument";
+    case PC_ERR_UNSTABLE_CONFIG: return "unstable configuration";
+    case PC_ERR_CAPACITY: return "capacity exceeded";
+    case PC_ERR_NONFINITE: return "non-finite or out-of-range value";
+    case PC_ERR_ECAP: return "electron energy above the collision bound";
+    case PC_ERR_GCAP: return "ion relative speed above the collision bound";
+    case PC_ERR_HIP: return "HIP runtime error";
+    case PC_ERR_POISONED: return "handle poisoned by an earlier device error";
+    case PC_ERR_WORKSPACE: return "workspace too small or misaligned";
+    case PC_ERR_IDS: return "particle id space exhausted";
+    default: return "unknown status";
+    }
+}
+
+const char* pc_last_error(void) { return g_last_error.c_str(); }
+
+}  // extern "C"

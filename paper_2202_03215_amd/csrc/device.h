@@ -1,0 +1,224 @@
+// device.h -- shared device-side definitions of the gfx950 PIC-MCC kernels.
+//
+// Column parameters, the counter-based random stream, isotropic directions,
+// Maxwellian draws and the synthetic cross sections.  Every floating-point
+// expression here is written in a fixed operation order and compiled without
+// FMA contraction (-ffp-contract=off) so that results do not depend on the
+// compiler's scheduling.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace pcdev {
+
+constexpr int kElectron = 0;
+constexpr int kIon = 1;
+
+// Philox stream tags (fourth counter word)
+constexpr uint32_t kStreamElectronStep = 0;
+constexpr uint32_t kStreamIonStep = 1;
+constexpr uint32_t kStreamElectronLoad = 2;
+constexpr uint32_t kStreamIonLoad = 3;
+
+// event codes (same values as the public header)
+constexpr uint8_t kEvNone = 0, kEvElastic = 1, kEvExcite = 2, kEvIonize = 3, kEvWall = 4,
+                  kEvAbsorb = 5, kEvCX = 6, kEvNull = 7;
+
+// device error bits
+constexpr uint32_t kErrECap = 1u, kErrGCap = 2u, kErrNuMax = 4u, kErrIds = 8u, kErrRange = 16u,
+                   kErrBirths = 32u, kErrLosses = 64u, kErrCapacity = 128u, kErrField = 256u;
+
+constexpr int64_t kUnit = int64_t(1) << 32;   // charge of one macroparticle, fixed point
+constexpr double kUnitD = 4294967296.0;
+
+struct Counters {
+    int64_t n[2];        // live particles
+    int64_t next_id[2];  // next id per species
+    int64_t step;        // index of the step being / to be executed
+    uint32_t err;        // sticky error bits
+    uint32_t pad0;
+    int64_t nb;          // ionizations recorded in the current step
+    int64_t nh[2];       // losses recorded in the current step
+    int64_t tail[2];     // compaction work counters (finish kernel)
+    int64_t pad1[5];
+};
+
+struct Birth {           // one ionization event (64 bytes)
+    uint32_t pid;
+    uint32_t pad;
+    double x;
+    double ve[3];        // ejected electron velocity
+    double vi[3];        // new ion velocity
+};
+
+struct Soa {             // one structure-of-arrays particle buffer
+    double* x;
+    double* vx;
+    double* vy;
+    double* vz;
+    uint32_t* id;
+};
+
+struct Params {
+    // grid
+    int32_t nc, nn, periodic, ion_subcycle;
+    double L, dx, inv_dx;
+    // time stepping and species
+    double dt, dti, qmdt_e, qmdt_i, c_eps, sig_a;
+    // collisions
+    double Ng, nu_max, P_null, T_we, T_wi, P_cx, g_cap, eps_cap, mr2;
+    double el_A, el_B, ex_U, sx4, iz_U, si4, opb_w;
+    int32_t el_pos, share_equal, poisson, pad0;
+    // field
+    double fpc, E0, V;
+    uint32_t key0, key1;
+    int64_t cap, max_births, max_holes;
+    Counters* cnt;
+    Birth* births;
+    uint32_t* holes[2];
+    uint32_t* lists;     // compaction scratch: 2 * max_holes entries
+    uint32_t* bitmap;    // compaction scratch: max_holes bits
+    int64_t* iz;         // ionizations per cell
+    double* E;           // n_nodes + 1 (periodic ghost E[nc] = E[0])
+    int32_t* sort_cnt;   // counting-sort histogram, n_cells
+    int32_t* sort_off;   // counting-sort cursors, n_cells
+};
+
+// ------------------------------------------------------------------ Philox
+// Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11): per round two 32x32->64
+// products of counter words 0 and 2 with the round multipliers, the high
+// halves XORed into words 1 and 3 and the key; key += Weyl constants.
+struct U4 {
+    uint32_t a, b, c, d;
+};
+
+__device__ __forceinline__ U4 philox10(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
+                                       uint32_t k0, uint32_t k1)
+{
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        const uint64_t p = uint64_t(0xD2511F53u) * c0;
+        const uint64_t q = uint64_t(0xCD9E8D57u) * c2;
+        const uint32_t n0 = uint32_t(q >> 32) ^ c1 ^ k0;
+        const uint32_t n2 = uint32_t(p >> 32) ^ c3 ^ k1;
+        c1 = uint32_t(q);
+        c3 = uint32_t(p);
+        c0 = n0;
+        c2 = n2;
+        k0 += 0x9E3779B9u;
+        k1 += 0xBB67AE85u;
+    }
+    return U4{c0, c1, c2, c3};
+}
+
+// open-interval uniforms: 52 bits from a word pair, or one 32-bit word
+__device__ __forceinline__ double unif52(uint32_t lo, uint32_t hi)
+{
+    const uint64_t r = (uint64_t(hi) << 32) | lo;
+    return (double(r >> 12) + 0.5) * 0x1p-52;
+}
+__device__ __forceinline__ double unif32(uint32_t w) { return (double(w) + 0.5) * 0x1p-32; }
+
+// Sequential words from Philox blocks 1, 2, 3, ... of (id, step, stream).
+struct WordStream {
+    uint32_t id, step, stream, k0, k1, block;
+    U4 buf;
+    int pos;
+    __device__ WordStream(uint32_t id_, uint32_t step_, uint32_t stream_, uint32_t k0_, uint32_t k1_)
+        : id(id_), step(step_), stream(stream_), k0(k0_), k1(k1_), block(0), buf{0, 0, 0, 0}, pos(4) {}
+    __device__ __forceinline__ uint32_t next()
+    {
+        if (pos == 4) {
+            block += 1;
+            buf = philox10(id, step, block, stream, k0, k1);
+            pos = 0;
+        }
+        const uint32_t w = pos == 0 ? buf.a : pos == 1 ? buf.b : pos == 2 ? buf.c : buf.d;
+        ++pos;
+        return w;
+    }
+    __device__ __forceinline__ double u() { return unif32(next()); }
+};
+
+// isotropic unit vector: Marsaglia (1972) point in the unit disk, at most 64
+// tries, then the +z pole
+__device__ __forceinline__ void isotropic(WordStream& ws, double& nx, double& ny, double& nz)
+{
+    for (int t = 0; t < 64; ++t) {
+        const double a = 2.0 * ws.u() - 1.0;
+        const double b = 2.0 * ws.u() - 1.0;
+        const double s = a * a + b * b;
+        if (s < 1.0) {
+            const double r = 2.0 * sqrt(1.0 - s);
+            nx = a * r;
+            ny = b * r;
+            nz = 1.0 - 2.0 * s;
+            return;
+        }
+    }
+    nx = 0.0;
+    ny = 0.0;
+    nz = 1.0;
+}
+
+// two standard normals by the Marsaglia-Bray polar method, at most 64 tries
+__device__ __forceinline__ void normal_pair(WordStream& ws, double& g0, double& g1)
+{
+    for (int t = 0; t < 64; ++t) {
+        const double a = 2.0 * ws.u() - 1.0;
+        const double b = 2.0 * ws.u() - 1.0;
+        const double s = a * a + b * b;
+        if (s < 1.0 && s > 0.0) {
+            const double f = sqrt(-2.0 * log(s) / s);
+            g0 = a * f;
+            g1 = b * f;
+            return;
+        }
+    }
+    g0 = 0.0;
+    g1 = 0.0;
+}
+
+// three normals: a full pair, then the first of a second pair
+__device__ __forceinline__ void normal3(WordStream& ws, double& g0, double& g1, double& g2)
+{
+    double h;
+    normal_pair(ws, g0, g1);
+    normal_pair(ws, g2, h);
+}
+
+// ---------------------------------------------------------- cross sections
+__device__ __forceinline__ double sigma_elastic(const Params& P, double eps)
+{
+    if (P.el_pos) return P.el_A + P.el_B * sqrt(eps);
+    return eps > 0.0 ? P.el_A + P.el_B / sqrt(eps) : P.el_A;
+}
+// Thomson-like lumped inelastic channel: 4 smax (U/eps)(1 - U/eps), eps > U
+__device__ __forceinline__ double sigma_inelastic(double eps, double U, double s4)
+{
+    if (eps > U) {
+        const double t = U / eps;
+        return s4 * t * (1.0 - t);
+    }
+    return 0.0;
+}
+
+// cell index and fraction of a position in [0, L)
+__device__ __forceinline__ int cell_frac(const Params& P, double x, double& f)
+{
+    const double s = x * P.inv_dx;
+    int j = int(s);
+    if (j > P.nc - 1) j = P.nc - 1;
+    if (j < 0) j = 0;   // never taken for x in [0, L); keeps reads in bounds
+    f = s - double(j);
+    return j;
+}
+
+__device__ __forceinline__ int64_t frac_units(double f)
+{
+    int64_t a = int64_t(f * kUnitD);
+    return a > kUnit ? kUnit : a;
+}
+
+}  // namespace pcdev

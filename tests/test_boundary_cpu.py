@@ -1,0 +1,56 @@
+"""CPU checks of the C-ABI boundary: the library loads, exports every symbol
+declared in include/pc.h, sizes workspaces and rejects bad configs (dt above
+0.2/w_pe or dx above the Debye length, section II of the paper; null-collision
+probability above 0.1).  No compute call is made here (no GPU)."""
+import os
+import re
+
+import pytest
+
+import workloads as W
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def native():
+    from paper_2202_03215_amd import build, native
+    if build.stale():
+        build.build()
+    return native
+
+
+def test_every_header_symbol_is_exported(native):
+    hdr = open(os.path.join(ROOT, "include", "pc.h")).read()
+    declared = set(re.findall(r"\b(pc_[a-z_]+)\s*\(", hdr))
+    assert declared, "no declarations found"
+    assert declared == set(native.EXPORTS)
+    lib = native.lib()
+    for name in declared:
+        assert hasattr(lib, name), name
+
+
+def test_sizes_scale_with_capacity(native):
+    s1 = native.query_sizes(W.small_bounded())
+    assert s1.n_nodes == 401 and s1.n_cells == 400
+    assert s1.capacity >= 20000 * 1.25
+    s2 = native.query_sizes(W.column_50cm())
+    assert s2.n_nodes == 5000
+    # two ping-pong buffers of 36 bytes per particle per species dominate
+    assert s2.workspace_bytes > 4 * 36 * 5_000_000
+
+
+@pytest.mark.parametrize("bad, status", [
+    (dict(dt=1e-9), "PC_ERR_UNSTABLE_CONFIG"),           # dt > 0.2 / w_pe
+    (dict(n_cells=40), "PC_ERR_UNSTABLE_CONFIG"),        # dx = 1 mm > lambda_De at 1e15
+    (dict(p_torr=40.0), "PC_ERR_UNSTABLE_CONFIG"),       # nu_max dt > 0.1
+    (dict(el_p=1.0), "PC_ERR_INVALID_ARG"),
+    (dict(n_cells=1), "PC_ERR_INVALID_ARG"),
+    (dict(n_cells=20000, L=0.2), "PC_ERR_INVALID_ARG"),  # field solve limited to 16384 nodes
+    (dict(ppc=0), "PC_ERR_INVALID_ARG"),
+])
+def test_bad_configs_rejected(native, bad, status):
+    cfg = W.with_(W.column_20cm(), **bad)
+    with pytest.raises(native.PcError) as e:
+        native.query_sizes(cfg)
+    assert status in str(e.value)
