@@ -39,8 +39,8 @@
 #define KB   1.380649e-23
 #define EPS0 8.8541878128e-12
 #define TORR (101325.0 / 760.0)
-#define FIX  4294967296.0          /* 2^32: fractional bits of the charge unit */
-#define FIXI ((int64_t)1 << 32)
+#define FIX  33554432.0            /* 2^25: fractional bits of the charge unit */
+#define FIXI ((int64_t)1 << 25)
 
 enum { ERR_RANGE = 16 };
 enum { ST_E_STEP = 0, ST_I_STEP = 1, ST_E_INIT = 2, ST_I_INIT = 3 };
@@ -263,7 +263,7 @@ pco_column* pco_create(const pco_config* cfg)
     c->qmdt_i = (QE * c->dti) / c->M;
     /* macroparticle weight (real particles per m^2 of column cross-section) */
     c->W = cfg->ppc > 0 ? cfg->n0 * c->dx / (double)cfg->ppc : 0.0;
-    /* field jump per fixed-point charge unit: e W 2^-32 / eps0  [V/m] */
+    /* field jump per fixed-point charge unit: e W 2^-25 / eps0  [V/m] */
     c->fpc = QE * c->W / FIX / EPS0;
     c->E0 = cfg->V / cfg->L;
     c->Vb = cfg->V;
@@ -319,8 +319,8 @@ void pco_destroy(pco_column* c)
 }
 
 /* ---------------------------------------------------------------- deposit */
-/* linear (cloud-in-cell) weighting into 64-bit fixed point with 32 fractional
- * bits: node j receives 2^32 - a and node j+1 receives a, a = trunc(f 2^32)
+/* linear (cloud-in-cell) weighting into 64-bit fixed point with 25 fractional
+ * bits: node j receives 2^25 - a and node j+1 receives a, a = trunc(f 2^25)
  * (reading of the "interpolation of the particle positions", section II). */
 static void deposit_one(const pco_column* c, double x, int64_t* rho)
 {
@@ -375,7 +375,7 @@ int pco_solve_field(const pco_column* c, const int64_t* rho_e, const int64_t* rh
     long double* phi = (long double*)calloc((size_t)nn + 2, sizeof(long double));
     long double* b = (long double*)calloc((size_t)nn + 2, sizeof(long double));
     if (!phi || !b) { free(phi); free(b); return -3; }
-    /* right-hand side dx^2 rho / eps0 with rho = e W Q 2^-32 / dx: dx fpc Q */
+    /* right-hand side dx^2 rho / eps0 with rho = e W Q 2^-25 / dx: dx fpc Q */
     const long double k = (long double)c->fpc * (long double)c->dx;
     const long double dx = c->dx, fpc = c->fpc;
     if (!c->periodic) {

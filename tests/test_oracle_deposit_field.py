@@ -17,7 +17,7 @@ from oracle.pco import Oracle
 
 QE = 1.602176634e-19
 EPS0 = 8.8541878128e-12
-FIX = 1 << 32
+FIX = 1 << 25
 
 
 def _col(bc, n_cells=37, L=0.0037, **kw):
@@ -35,7 +35,7 @@ def test_deposit_total_charge_exact(bc):
 
 @pytest.mark.parametrize("bc", ["bounded", "periodic"])
 def test_deposit_matches_exact_rational_weights(bc):
-    # brute force: node j+1 receives floor(frac(x/dx) 2^32) up to one unit
+    # brute force: node j+1 receives floor(frac(x/dx) 2^25) up to one unit
     # (the oracle forms x/dx as x * (n/L) in double)
     nc, L = 37, 0.0037
     o = _col(bc, n_cells=nc, L=L)
@@ -65,7 +65,7 @@ def test_deposit_on_node_goes_to_that_node_only():
 def test_deposit_order_independent_and_mirror():
     o = _col("bounded", n_cells=16, L=1.0)
     rng = np.random.default_rng(2)
-    # dyadic positions: x*16 has at most 20 fractional bits, so f*2^32 is exact
+    # dyadic positions: x*16 has at most 20 fractional bits, so f*2^25 is exact
     x = rng.integers(0, 16 << 20, size=4000) / float(16 << 20)
     r1 = o.deposit(x)
     r2 = o.deposit(x[rng.permutation(x.size)])
@@ -105,11 +105,11 @@ def test_field_uniform_charge_bounded_parabola():
     # parabola phi = V x/L + rho x (L - x) / (2 eps0)
     nc, L, V = 200, 0.02, 7.0
     o = _col("bounded", n_cells=nc, L=L, V=V)
-    q = np.full(nc + 1, 3 << 33, dtype=np.int64)
+    q = np.full(nc + 1, 3 << 26, dtype=np.int64)
     z = np.zeros(nc + 1, dtype=np.int64)
     phi, E = o.solve_field(z, q)
     dx = L / nc
-    rho = QE * o.constant("W") * (3 << 33) / FIX / dx
+    rho = QE * o.constant("W") * (3 << 26) / FIX / dx
     x = np.arange(nc + 1) * dx
     ref = V * x / L + rho * x * (L - x) / (2 * EPS0)
     assert np.abs(phi - ref).max() <= 1e-11 * np.abs(ref).max()
