@@ -28,8 +28,8 @@
  *  - Particle state is structure-of-arrays, FP64: x [m] in [0, L), vx, vy,
  *    vz [m/s] (vx is the leapfrog half-step velocity), id (uint32).  Node
  *    arrays have pc_sizes.n_nodes entries: n_cells + 1 (bounded) or n_cells
- *    (periodic).  Charges are int64 fixed point with 32 fractional bits: a
- *    macroparticle contributes exactly 2^32 units split between its two
+ *    (periodic).  Charges are int64 fixed point with 25 fractional bits: a
+ *    macroparticle contributes exactly 2^25 units split between its two
  *    nodes.
  */
 #ifndef PC_H
@@ -116,7 +116,10 @@ pc_status pc_init_column(const pc_config* cfg, void* workspace, size_t bytes,
  * deposit), ions every ion_subcycle steps with dt_i = ion_subcycle dt,
  * removal of losses, append of ionization products (ids by rank of the
  * parent id), field solve; a per-cell counting sort every sort_interval
- * steps (no effect on results). */
+ * steps (no effect on results).  On a non-null stream, whole periods of
+ * lcm(2, 2 ion_subcycle, 2 sort_interval) steps are captured once into a
+ * HIP graph and replayed; event buffers or an enabled kernel timer make the
+ * launches eager.  Results are bitwise identical either way. */
 pc_status pc_step(pc_handle h, int64_t n_steps);
 
 /* Deposit n positions (device FP64, all in [0, L)) with linear weighting
@@ -170,8 +173,9 @@ pc_status pc_set_events(pc_handle h, uint8_t* ev_e, int64_t len_e, uint8_t* ev_i
 /* Kernel timer for roofline measurements: with max_launches > 0, pc_step
  * brackets each launch of the electron advance kernel (the dominant kernel:
  * gather, push, collisions, deposit) with a pair of HIP events on the
- * column's stream, up to max_launches launches.  The event pool is created
- * here, never inside pc_step; 0 disables the timer and frees the pool. */
+ * column's stream, up to max_launches launches (launches are then eager, not
+ * graph-replayed).  The event pool is created here, never inside pc_step;
+ * 0 disables the timer and frees the pool. */
 pc_status pc_timer_enable(pc_handle h, int64_t max_launches);
 /* Wait for the recorded launches and return their summed duration [ms] and
  * count; resets the timer for the next window (blocking). */

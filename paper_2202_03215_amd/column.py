@@ -5,6 +5,10 @@ tensors) and the HIP stream; the C ABI (include/pc.h) does the work.  Method
 names follow the C entry points: init_column (the constructor), step,
 deposit, solve_field, moments, get_state / set_state, get_field / set_field,
 set_counters, set_events, counts, sync.
+
+Each column runs on its own default-priority stream (so that the library can
+replay whole step periods as a HIP graph); every method orders that stream
+against torch's current stream in both directions.
 """
 from __future__ import annotations
 
@@ -36,11 +40,12 @@ class Column:
         self.nn = int(self.sizes.n_nodes)
         self.nc = int(self.sizes.n_cells)
         self.capacity = int(self.sizes.capacity)
-        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
         with torch.cuda.device(self.device):
+            self.stream = stream if stream is not None else torch.cuda.Stream(self.device)
             self.workspace = torch.empty(int(self.sizes.workspace_bytes), dtype=torch.uint8,
                                          device=self.device)
         h = C.c_void_p()
+        self._in()
         N.check(N.lib().pc_init_column(C.byref(self._c), self.workspace.data_ptr(),
                                        int(self.sizes.workspace_bytes),
                                        C.c_void_p(self.stream.cuda_stream), C.byref(h)))
@@ -53,9 +58,23 @@ class Column:
             N.lib().pc_destroy(h)
             self.h = None
 
+    # ------------------------------------------------------- stream order
+    def _in(self, *tensors):
+        """Column stream waits for torch's stream (inputs produced there)."""
+        self.stream.wait_stream(torch.cuda.current_stream(self.device))
+        for t in tensors:
+            if t is not None:
+                t.record_stream(self.stream)
+
+    def _out(self):
+        """Torch's stream waits for the column stream (outputs written there)."""
+        torch.cuda.current_stream(self.device).wait_stream(self.stream)
+
     # ------------------------------------------------------------ stepping
     def step(self, n: int = 1) -> None:
+        self._in()
         N.check(N.lib().pc_step(self.h, int(n)))
+        self._out()
 
     def sync(self) -> None:
         N.check(N.lib().pc_sync(self.h))
@@ -73,7 +92,9 @@ class Column:
     def deposit(self, x: torch.Tensor) -> torch.Tensor:
         x = x.to(self.device, torch.float64).contiguous()
         rho = self._empty(self.nn, torch.int64)
+        self._in(x, rho)
         N.check(N.lib().pc_deposit(self.h, _ptr(x), x.numel(), _ptr(rho)))
+        self._out()
         return rho
 
     def solve_field(self, rho_e: torch.Tensor, rho_i: torch.Tensor, want_phi: bool = True):
@@ -81,13 +102,17 @@ class Column:
         ri = rho_i.to(self.device, torch.int64).contiguous()
         E = self._empty(self.nn, torch.float64)
         phi = self._empty(self.nn, torch.float64) if want_phi else None
+        self._in(re, ri, E, phi)
         N.check(N.lib().pc_solve_field(self.h, _ptr(re), _ptr(ri), _ptr(phi), _ptr(E)))
+        self._out()
         return phi, E
 
     def moments(self, cells_per_group: int = 1, reset_iz: bool = False) -> torch.Tensor:
         ng = (self.nc + cells_per_group - 1) // cells_per_group
         out = self._empty(7 * self.nc + ng * 240, torch.int64)
+        self._in(out)
         N.check(N.lib().pc_moments(self.h, int(cells_per_group), int(reset_iz), _ptr(out)))
+        self._out()
         return out
 
     # ------------------------------------------------------------ state I/O
@@ -95,13 +120,16 @@ class Column:
         n = self.counts()["n"][species]
         x, vx, vy, vz = (self._empty(n, torch.float64) for _ in range(4))
         ids = self._empty(n, torch.int32)
+        self._in(x, vx, vy, vz, ids)
         N.check(N.lib().pc_get_state(self.h, int(species), _ptr(x), _ptr(vx), _ptr(vy), _ptr(vz),
                                      _ptr(ids), n))
+        self._out()
         return x, vx, vy, vz, ids
 
     def set_state(self, species: int, x, vx, vy, vz, ids) -> None:
         ts = [torch.as_tensor(a).to(self.device, torch.float64).contiguous() for a in (x, vx, vy, vz)]
         it = torch.as_tensor(ids).to(torch.int64).to(torch.int32).to(self.device).contiguous()
+        self._in(*ts, it)
         N.check(N.lib().pc_set_state(self.h, int(species), it.numel(), *[_ptr(t) for t in ts],
                                      _ptr(it)))
         torch.cuda.synchronize(self.device)
@@ -113,11 +141,14 @@ class Column:
         E = self._empty(self.nn, torch.float64)
         re = self._empty(self.nn, torch.int64)
         ri = self._empty(self.nn, torch.int64)
+        self._in(E, re, ri)
         N.check(N.lib().pc_get_field(self.h, _ptr(E), _ptr(re), _ptr(ri)))
+        self._out()
         return E, re, ri
 
     def set_field(self, E) -> None:
         e = torch.as_tensor(E).to(self.device, torch.float64).contiguous()
+        self._in(e)
         N.check(N.lib().pc_set_field(self.h, _ptr(e)))
         torch.cuda.synchronize(self.device)
 
@@ -125,6 +156,7 @@ class Column:
         """Allocate per-id event buffers (uint8) that each step fills."""
         ev_e = torch.zeros(len_e, dtype=torch.uint8, device=self.device)
         ev_i = torch.zeros(len_i, dtype=torch.uint8, device=self.device)
+        self._in(ev_e, ev_i)
         N.check(N.lib().pc_set_events(self.h, _ptr(ev_e), len_e, _ptr(ev_i), len_i))
         self._events = (ev_e, ev_i)
         return self._events

@@ -162,7 +162,7 @@ pc_status derive(const pc_config* c, Derived* d)
 }
 
 struct Layout {
-    int64_t counters, soa[2][2][5], rho[2][2], E, births, holes[2], lists, bitmap, iz, sort_cnt, sort_off, total;
+    int64_t counters, soa[2][2][5], rho[2][2], E, births, holes[2], cand, lists, bitmap, iz, sort_cnt, sort_off, total;
 };
 
 Layout layout(const Derived& d)
@@ -186,6 +186,7 @@ Layout layout(const Derived& d)
     L.births = take(d.max_births * int64_t(sizeof(pcdev::Birth)));
     L.holes[0] = take(d.max_holes * 4);
     L.holes[1] = take(d.max_holes * 4);
+    L.cand = take(d.cap * 4);
     L.lists = take(2 * d.max_holes * 4);
     L.bitmap = take((d.max_holes / 32 + 1) * 4);
     L.iz = take(int64_t(d.nc) * 8);
@@ -210,10 +211,13 @@ struct pc_column {
     int poisoned;
     uint8_t* ev[2];
     int64_t evlen[2];
-    int grid;
+    int grid;     // blocks of the streaming particle kernels
     Counters host_cnt;
     std::vector<hipEvent_t> tev;   // timer pool: 2 events per launch
     int64_t tcount;
+    int use_graphs;                // replay whole buffer periods as a HIP graph
+    hipGraphExec_t gexec;
+    int64_t gkey[6];               // bookkeeping state the graph was captured from
 };
 
 namespace {
@@ -351,6 +355,7 @@ pc_status pc_init_column(const pc_config* cfg, void* workspace, size_t bytes, vo
     P.births = reinterpret_cast<pcdev::Birth*>(base + L.births);
     P.holes[0] = reinterpret_cast<uint32_t*>(base + L.holes[0]);
     P.holes[1] = reinterpret_cast<uint32_t*>(base + L.holes[1]);
+    P.cand = reinterpret_cast<uint32_t*>(base + L.cand);
     P.lists = reinterpret_cast<uint32_t*>(base + L.lists);
     P.bitmap = reinterpret_cast<uint32_t*>(base + L.bitmap);
     P.iz = reinterpret_cast<int64_t*>(base + L.iz);
@@ -361,6 +366,8 @@ pc_status pc_init_column(const pc_config* cfg, void* workspace, size_t bytes, vo
                                      : int(std::min<int64_t>(4096, std::max<int64_t>(1, (d.cap + 255) / 256)));
     h->cur[0] = h->cur[1] = 0;
     h->re_cur = h->ri_cur = 0;
+    h->use_graphs = 1;
+    h->gexec = nullptr;
     h->step = 0;
 
     auto cleanup = [&](pc_status st) {
@@ -391,34 +398,129 @@ pc_status pc_init_column(const pc_config* cfg, void* workspace, size_t bytes, vo
     return PC_OK;
 }
 
+// Enqueue one full time step on the column's stream and advance the host-side
+// bookkeeping (step index, charge and sort buffer parities).  With time_it,
+// the electron advance launch is bracketed by timer pair `slot`.
+static pc_status enqueue_step(pc_column* h, bool time_it, int64_t slot)
+{
+    const int S = h->cfg.ion_subcycle;
+    const int K = h->cfg.sort_interval;
+    const bool ion = h->step % S == 0;
+    int64_t* re_new = h->rho[0][1 - h->re_cur];
+    int64_t* re_old = h->rho[0][h->re_cur];
+    int64_t* ri_use = ion ? h->rho[1][1 - h->ri_cur] : h->rho[1][h->ri_cur];
+    int64_t* ri_old = ion ? h->rho[1][h->ri_cur] : nullptr;
+    const Soa se = soa_of(h, 0), si = soa_of(h, 1);
+    if (time_it) HIPCHK(hipEventRecord(h->tev[2 * slot], h->st));
+    HIPCHK(pclaunch::advance(h->P, 0, se, re_new, h->ev[0], h->evlen[0], h->grid, h->st));
+    if (time_it) HIPCHK(hipEventRecord(h->tev[2 * slot + 1], h->st));
+    if (ion) HIPCHK(pclaunch::advance(h->P, 1, si, ri_use, h->ev[1], h->evlen[1], h->grid, h->st));
+    HIPCHK(pclaunch::finish(h->P, se, si, re_new, ri_use, re_old, ri_old, h->st));
+    h->re_cur = 1 - h->re_cur;
+    if (ion) h->ri_cur = 1 - h->ri_cur;
+    h->step += 1;
+    if (K > 0 && h->step % K == 0) return run_sort(h);
+    return PC_OK;
+}
+
+static int64_t gcd64(int64_t a, int64_t b)
+{
+    while (b) {
+        const int64_t t = a % b;
+        a = b;
+        b = t;
+    }
+    return a;
+}
+
+// Steps after which every buffer parity returns: electron charge buffers
+// alternate each step, ion charge buffers each ion step, particle buffers
+// each sort.
+static int64_t graph_period(const pc_column* h)
+{
+    auto lcm = [](int64_t a, int64_t b) { return a / gcd64(a, b) * b; };
+    int64_t p = lcm(2, 2 * int64_t(h->cfg.ion_subcycle));
+    if (h->cfg.sort_interval > 0) p = lcm(p, 2 * int64_t(h->cfg.sort_interval));
+    return p;
+}
+
+static void drop_graph(pc_column* h)
+{
+    if (h->gexec) (void)hipGraphExecDestroy(h->gexec);
+    h->gexec = nullptr;
+}
+
+// Capture `period` steps from the current bookkeeping state into a graph
+// (host bookkeeping is restored: nothing executes during capture).
+static pc_status capture_period(pc_column* h, int64_t period)
+{
+    const int64_t step = h->step;
+    const int re = h->re_cur, ri = h->ri_cur, c0 = h->cur[0], c1 = h->cur[1];
+    drop_graph(h);
+    hipError_t e = hipStreamBeginCapture(h->st, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        h->use_graphs = 0;   // e.g. the legacy default stream: stay eager
+        return PC_OK;
+    }
+    pc_status st = PC_OK;
+    for (int64_t k = 0; k < period && st == PC_OK; ++k) st = enqueue_step(h, false, 0);
+    hipGraph_t g = nullptr;
+    e = hipStreamEndCapture(h->st, &g);
+    h->step = step;
+    h->re_cur = re;
+    h->ri_cur = ri;
+    h->cur[0] = c0;
+    h->cur[1] = c1;
+    if (st != PC_OK) {
+        if (g) (void)hipGraphDestroy(g);
+        return st;
+    }
+    if (e != hipSuccess) return hip_fail(e, "hipStreamEndCapture");
+    e = hipGraphInstantiate(&h->gexec, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (e != hipSuccess) {
+        h->gexec = nullptr;
+        return hip_fail(e, "hipGraphInstantiate");
+    }
+    h->gkey[0] = step % period;
+    h->gkey[1] = re;
+    h->gkey[2] = ri;
+    h->gkey[3] = c0;
+    h->gkey[4] = c1;
+    h->gkey[5] = 0;
+    return PC_OK;
+}
+
 pc_status pc_step(pc_handle h, int64_t n_steps)
 {
     if (!h || n_steps < 0) return fail(PC_ERR_INVALID_ARG, "bad handle or step count");
     if (h->poisoned) return fail(PC_ERR_POISONED, "an earlier device error is pending");
-    const int S = h->cfg.ion_subcycle;
-    const int K = h->cfg.sort_interval;
-    for (int64_t k = 0; k < n_steps; ++k) {
-        const bool ion = h->step % S == 0;
-        int64_t* re_new = h->rho[0][1 - h->re_cur];
-        int64_t* re_old = h->rho[0][h->re_cur];
-        int64_t* ri_use = ion ? h->rho[1][1 - h->ri_cur] : h->rho[1][h->ri_cur];
-        int64_t* ri_old = ion ? h->rho[1][h->ri_cur] : nullptr;
-        const Soa se = soa_of(h, 0), si = soa_of(h, 1);
-        const bool timed = h->tcount < int64_t(h->tev.size() / 2);
-        if (timed) HIPCHK(hipEventRecord(h->tev[2 * h->tcount], h->st));
-        HIPCHK(pclaunch::advance(h->P, 0, se, re_new, h->ev[0], h->evlen[0], h->grid, h->st));
-        if (timed) {
-            HIPCHK(hipEventRecord(h->tev[2 * h->tcount + 1], h->st));
-            h->tcount += 1;
-        }
-        if (ion) HIPCHK(pclaunch::advance(h->P, 1, si, ri_use, h->ev[1], h->evlen[1], h->grid, h->st));
-        HIPCHK(pclaunch::finish(h->P, se, si, re_new, ri_use, re_old, ri_old, h->st));
-        h->re_cur = 1 - h->re_cur;
-        if (ion) h->ri_cur = 1 - h->ri_cur;
-        h->step += 1;
-        if (K > 0 && h->step % K == 0) {
-            const pc_status s = run_sort(h);
+    const int64_t period = graph_period(h);
+    const bool timer_on = !h->tev.empty();
+    const int64_t tcap = int64_t(h->tev.size() / 2);
+    // graph replay needs a capturable (non-null) stream; event buffers and the
+    // kernel timer run eagerly (graph-recorded events have no readable time)
+    const bool graphs = h->use_graphs && h->st != nullptr && !h->ev[0] && !h->ev[1] &&
+                        period <= 4096 && !timer_on;
+    int64_t left = n_steps;
+    while (left > 0) {
+        if (graphs && h->use_graphs && left >= period) {
+            const int64_t key[6] = {h->step % period, h->re_cur, h->ri_cur, h->cur[0], h->cur[1], 0};
+            if (!h->gexec || std::memcmp(key, h->gkey, sizeof(key)) != 0) {
+                const pc_status s = capture_period(h, period);
+                if (s != PC_OK) return s;
+                if (!h->gexec) continue;   // capture unavailable: eager from now on
+            }
+            HIPCHK(hipGraphLaunch(h->gexec, h->st));
+            h->step += period;   // every buffer parity is back where it started
+            left -= period;
+        } else {
+            const bool t = timer_on && h->tcount < tcap;
+            const pc_status s = enqueue_step(h, t, h->tcount);
             if (s != PC_OK) return s;
+            if (t) h->tcount += 1;
+            left -= 1;
         }
     }
     return PC_OK;
@@ -551,6 +653,7 @@ pc_status pc_set_field(pc_handle h, const double* E)
 pc_status pc_set_events(pc_handle h, uint8_t* ev_e, int64_t len_e, uint8_t* ev_i, int64_t len_i)
 {
     if (!h || len_e < 0 || len_i < 0) return fail(PC_ERR_INVALID_ARG, "bad event buffers");
+    drop_graph(h);
     h->ev[0] = ev_e;
     h->evlen[0] = ev_e ? len_e : 0;
     h->ev[1] = ev_i;
@@ -574,6 +677,7 @@ pc_status pc_timer_enable(pc_handle h, int64_t max_launches)
 {
     if (!h || max_launches < 0 || max_launches > (int64_t(1) << 24)) return fail(PC_ERR_INVALID_ARG, "bad timer size");
     HIPCHK(hipStreamSynchronize(h->st));
+    drop_graph(h);
     for (hipEvent_t e : h->tev) HIPCHK(hipEventDestroy(e));
     h->tev.clear();
     h->tcount = 0;
@@ -604,6 +708,7 @@ pc_status pc_timer_read(pc_handle h, double* total_ms, int64_t* launches)
 void pc_destroy(pc_handle h)
 {
     if (!h) return;
+    drop_graph(h);
     for (hipEvent_t e : h->tev) (void)hipEventDestroy(e);
     delete h;
 }

@@ -29,8 +29,10 @@ constexpr uint8_t kEvNone = 0, kEvElastic = 1, kEvExcite = 2, kEvIonize = 3, kEv
 constexpr uint32_t kErrECap = 1u, kErrGCap = 2u, kErrNuMax = 4u, kErrIds = 8u, kErrRange = 16u,
                    kErrBirths = 32u, kErrLosses = 64u, kErrCapacity = 128u, kErrField = 256u;
 
-constexpr int64_t kUnit = int64_t(1) << 32;   // charge of one macroparticle, fixed point
-constexpr double kUnitD = 4294967296.0;
+// charge of one macroparticle in fixed point: 25 fractional bits, so that the
+// weights of 64 lanes (each <= 2^25) sum below 2^32
+constexpr int64_t kUnit = int64_t(1) << 25;
+constexpr double kUnitD = 33554432.0;
 
 struct Counters {
     int64_t n[2];        // live particles
@@ -40,16 +42,16 @@ struct Counters {
     uint32_t pad0;
     int64_t nb;          // ionizations recorded in the current step
     int64_t nh[2];       // losses recorded in the current step
-    int64_t tail[2];     // compaction work counters (finish kernel)
-    int64_t pad1[5];
+    int64_t pad1[7];
 };
 
 struct Birth {           // one ionization event (64 bytes)
-    uint32_t pid;
-    uint32_t pad;
-    double x;
-    double ve[3];        // ejected electron velocity
-    double vi[3];        // new ion velocity
+    uint32_t pid;        // id of the ionizing electron
+    uint32_t slot;       // its array slot during the step
+    double x;            // position
+    double eps;          // energy before the collision [eV]
+    double vs[3];        // scratch: scattered velocity (large-step fallback)
+    double pad;
 };
 
 struct Soa {             // one structure-of-arrays particle buffer
@@ -77,6 +79,8 @@ struct Params {
     Counters* cnt;
     Birth* births;
     uint32_t* holes[2];
+    uint32_t* cand;      // electron collision candidates (slot indices): each block of
+                         // the push kernel lists its own from the start of its chunk
     uint32_t* lists;     // compaction scratch: 2 * max_holes entries
     uint32_t* bitmap;    // compaction scratch: max_holes bits
     int64_t* iz;         // ionizations per cell

@@ -14,7 +14,7 @@ constexpr int kAdvBlock = 256;   // threads per block of the particle kernels
 constexpr int kWindow = 256;     // LDS deposit window (nodes) per block
 constexpr int kHalo = 64;        // window starts this many nodes before the chunk
 constexpr int kOneBlock = 1024;  // threads of the single-workgroup kernels
-constexpr int kMaxSeg = 16;      // nodes per thread in the field solve (n_nodes <= 16384)
+constexpr int kMaxSeg = 8;       // nodes per thread in the field solve (n_nodes <= 8192)
 
 __device__ __forceinline__ int lane_id() { return __lane_id(); }
 
@@ -23,12 +23,8 @@ __device__ __forceinline__ uint32_t lanes_below(uint64_t m)
     return __builtin_amdgcn_mbcnt_hi(uint32_t(m >> 32), __builtin_amdgcn_mbcnt_lo(uint32_t(m), 0u));
 }
 
-__device__ __forceinline__ double wave_sum(double v)
-{
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
-    return v;
-}
+// DPP wavefront reduction from the device library (all lanes participate)
+extern "C" __device__ uint64_t __ockl_wfred_add_u64(uint64_t);
 
 __device__ __forceinline__ void set_err(const Params& P, uint32_t bits) { atomicOr(&P.cnt->err, bits); }
 
@@ -44,185 +40,332 @@ __device__ __forceinline__ void add_node(unsigned long long* win, int wbase, int
         atomicAdd((unsigned long long*)&rho[node], (unsigned long long)v);
 }
 
-// Wave-aggregated CIC deposit: lanes sharing a cell are summed first (count
-// times 2^32 minus the summed fractions to node j, the summed fractions to
-// node j+1), up to two distinct cells per wave; the rest deposit per lane.
+// Wave-aggregated CIC deposit.  The wave's two leading cells (those of the
+// first pending lane and of the first lane outside that cell) are reduced
+// together: weights of the first cell in the low 32 bits, of the second in
+// the high 32 bits of one 64-bit DPP reduction (each sum <= 64 * 2^25 < 2^32,
+// so no carry crosses).  Node j of a cell receives count * 2^25 minus the
+// summed weights, node j+1 the summed weights.  Lanes in further cells
+// deposit one by one.  Integer sums: the result is independent of order.
 __device__ __forceinline__ void deposit_wave(const Params& P, unsigned long long* win, int wbase,
                                              int64_t* rho, bool alive, int j, int64_t a)
 {
-    bool pend = alive;
-#pragma unroll
-    for (int it = 0; it < 2; ++it) {
-        const uint64_t m = __ballot(pend);
-        if (m == 0) return;
-        const int leader = __ffsll((unsigned long long)m) - 1;
-        const int jr = __builtin_amdgcn_readlane(j, leader);
-        const bool mine = pend && j == jr;
-        const uint64_t mm = __ballot(mine);
-        const double s = wave_sum(mine ? double(a) : 0.0);
-        if (lane_id() == leader) {
-            const int64_t sa = int64_t(s);
-            const int64_t cntm = int64_t(__popcll((unsigned long long)mm));
-            int j1 = jr + 1;
-            if (P.periodic && j1 == P.nc) j1 = 0;
-            add_node(win, wbase, rho, jr, cntm * kUnit - sa);
-            add_node(win, wbase, rho, j1, sa);
-        }
-        pend = pend && !mine;
+    const uint64_t m = __ballot(alive);
+    if (m == 0) return;
+    const int l1 = __ffsll((unsigned long long)m) - 1;
+    const int j1 = __builtin_amdgcn_readlane(j, l1);
+    const bool in1 = alive && j == j1;
+    const uint64_t m1 = __ballot(in1);
+    const uint64_t rest = m & ~m1;
+    int l2 = 64, j2 = -1;
+    if (rest != 0) {
+        l2 = __ffsll((unsigned long long)rest) - 1;
+        j2 = __builtin_amdgcn_readlane(j, l2);
     }
-    if (pend) {
-        int j1 = j + 1;
-        if (P.periodic && j1 == P.nc) j1 = 0;
+    const bool in2 = alive && !in1 && j == j2;
+    const uint64_t m2 = __ballot(in2);
+    const uint64_t packed = in1 ? uint64_t(a) : (in2 ? uint64_t(a) << 32 : 0ull);
+    const uint64_t sum = __ockl_wfred_add_u64(packed);
+    if (lane_id() == l1) {
+        const int64_t s1 = int64_t(sum & 0xFFFFFFFFull), s2 = int64_t(sum >> 32);
+        const int64_t c1 = int64_t(__popcll((unsigned long long)m1)) * kUnit;
+        const int64_t c2 = int64_t(__popcll((unsigned long long)m2)) * kUnit;
+        int n1 = j1 + 1;
+        if (P.periodic && n1 == P.nc) n1 = 0;
+        if (m2 == 0) {
+            add_node(win, wbase, rho, j1, c1 - s1);
+            add_node(win, wbase, rho, n1, s1);
+        } else {
+            int n2 = j2 + 1;
+            if (P.periodic && n2 == P.nc) n2 = 0;
+            if (n1 == j2) {            // adjacent cells share node j1 + 1
+                add_node(win, wbase, rho, j1, c1 - s1);
+                add_node(win, wbase, rho, n1, s1 + c2 - s2);
+                add_node(win, wbase, rho, n2, s2);
+            } else if (n2 == j1) {
+                add_node(win, wbase, rho, j2, c2 - s2);
+                add_node(win, wbase, rho, j1, s2 + c1 - s1);
+                add_node(win, wbase, rho, n1, s1);
+            } else {
+                add_node(win, wbase, rho, j1, c1 - s1);
+                add_node(win, wbase, rho, n1, s1);
+                add_node(win, wbase, rho, j2, c2 - s2);
+                add_node(win, wbase, rho, n2, s2);
+            }
+        }
+    }
+    if (alive && !in1 && !in2) {
+        int j1n = j + 1;
+        if (P.periodic && j1n == P.nc) j1n = 0;
         add_node(win, wbase, rho, j, kUnit - a);
-        add_node(win, wbase, rho, j1, a);
+        add_node(win, wbase, rho, j1n, a);
     }
 }
 
-// append the flagged lanes' values to a global list with one atomic per wave
+// append the flagged lanes to a global list with one atomic per wave;
+// returns the lane's list position or -1
 __device__ __forceinline__ int64_t wave_append(bool flag, int64_t* counter)
 {
     const uint64_t m = __ballot(flag);
     if (m == 0) return -1;
     const int leader = __ffsll((unsigned long long)m) - 1;
     unsigned long long base = 0;
-    if (lane_id() == leader) base = atomicAdd((unsigned long long*)counter, (unsigned long long)__popcll((unsigned long long)m));
+    if (lane_id() == leader)
+        base = atomicAdd((unsigned long long*)counter, (unsigned long long)__popcll((unsigned long long)m));
     base = __shfl(base, leader);
     return flag ? int64_t(base) + int64_t(lanes_below(m)) : -1;
 }
 
-// ---------------------------------------------------------------- advance
-// One species, one step: gather, leapfrog push, boundary, radial sink,
-// null-collision MCC, ionization / loss records, fused fixed-point deposit.
-template <int S>
-__global__ __launch_bounds__(kAdvBlock) void k_advance(Params P, Soa sp, int64_t* __restrict__ rho,
-                                                      uint8_t* __restrict__ ev, int64_t evlen)
+// contiguous chunk of a particle array handled by this block (64-aligned)
+__device__ __forceinline__ void block_chunk(int64_t n, int64_t& beg, int64_t& end)
+{
+    const int64_t per = ((n + gridDim.x - 1) / gridDim.x + 63) & ~int64_t(63);
+    beg = int64_t(blockIdx.x) * per;
+    end = beg + per < n ? beg + per : n;
+}
+
+// periodic reinjection / absorbing walls; returns false if the particle left
+__device__ __forceinline__ bool apply_boundary(const Params& P, double& x, uint8_t& code)
+{
+    if (P.periodic) {
+        if (x >= P.L) x -= P.L;
+        else if (x < 0.0) {
+            x += P.L;
+            if (x >= P.L) x = 0.0;
+        }
+        if (!(x >= 0.0 && x < P.L)) {
+            set_err(P, kErrRange);
+            x = 0.0;
+        }
+        return true;
+    }
+    if (x >= 0.0 && x < P.L) return true;
+    if (!(x < 0.0 || x >= P.L)) set_err(P, kErrRange);
+    code = kEvAbsorb;
+    return false;
+}
+
+// -------------------------------------------------------- electron collide
+// One collision candidate: choose the process with u1 nu_max against the
+// cumulative collision frequencies (elastic, excitation, ionization, else
+// null), then scatter.  Ionizations (rare) are listed with the parent's slot,
+// position and energy; their kinematics run in the finish kernel.
+template <bool EV>
+__device__ __forceinline__ void collide_one(const Params& P, const Soa& sp, uint8_t* __restrict__ ev,
+                                            int64_t evlen, uint32_t step, bool act, uint32_t i)
+{
+    const uint32_t stream = kStreamElectronStep;
+    bool born = false;
+    uint32_t id = 0;
+    int jn = 0;
+    double x = 0.0, epsb = 0.0;
+    if (act) {
+        double vx = sp.vx[i], vy = sp.vy[i], vz = sp.vz[i];
+        id = sp.id[i];
+        const U4 w = philox10(id, step, 0u, stream, P.key0, P.key1);
+        const double u1 = unif52(w.c, w.d);
+        const double v2 = (vx * vx + vy * vy) + vz * vz;
+        const double eps = P.c_eps * v2;
+        const double v = sqrt(v2);
+        if (eps > P.eps_cap) set_err(P, kErrECap);
+        const double s_el = sigma_elastic(P, eps);
+        const double s_ex = sigma_inelastic(eps, P.ex_U, P.sx4);
+        const double s_iz = sigma_inelastic(eps, P.iz_U, P.si4);
+        const double c1 = s_el * v * P.Ng;
+        const double c2 = c1 + s_ex * v * P.Ng;
+        const double c3 = c2 + s_iz * v * P.Ng;
+        if (c3 > P.nu_max) set_err(P, kErrNuMax);
+        const double R = u1 * P.nu_max;
+        uint8_t code = kEvNull;
+        if (R < c3) {
+            if (R < c2) {
+                WordStream ws(id, step, stream, P.key0, P.key1);
+                double nx, ny, nz, vn;
+                isotropic(ws, nx, ny, nz);
+                if (R < c1) {
+                    code = kEvElastic;
+                    const double cosx = ((vx * nx + vy * ny) + vz * nz) / v;
+                    const double fac = 1.0 - P.mr2 * (1.0 - cosx);
+                    vn = v * sqrt(fac);
+                } else {
+                    code = kEvExcite;
+                    vn = sqrt((eps - P.ex_U) / P.c_eps);
+                }
+                sp.vx[i] = vn * nx;
+                sp.vy[i] = vn * ny;
+                sp.vz[i] = vn * nz;
+            } else {
+                code = kEvIonize;
+                x = sp.x[i];
+                epsb = eps;
+                double f;
+                jn = cell_frac(P, x, f);
+                born = true;
+            }
+        }
+        if (EV && int64_t(id) < evlen) ev[id] = code;
+    }
+    const int64_t bp = wave_append(born, &P.cnt->nb);
+    if (bp >= 0) {
+        if (bp < P.max_births) {
+            Birth b;
+            b.pid = id;
+            b.slot = i;
+            b.x = x;
+            b.eps = epsb;
+            b.vs[0] = 0.0; b.vs[1] = 0.0; b.vs[2] = 0.0;
+            b.pad = 0.0;
+            P.births[bp] = b;
+            atomicAdd((unsigned long long*)&P.iz[jn], 1ull);
+        } else {
+            set_err(P, kErrBirths);
+        }
+    }
+}
+
+// ------------------------------------------------------------ electron push
+// Streaming pass over all electrons: CIC gather, leapfrog push, boundary,
+// radial sink, null-collision candidate test (u0 < P_null), fused
+// fixed-point deposit.  Candidates are listed in the block's segment and
+// collided in a second phase of the same block; collisions change only
+// velocities, so the deposit of phase 1 is final.
+template <bool EV>
+__global__ __launch_bounds__(kAdvBlock) void k_push_e(Params P, Soa sp, int64_t* __restrict__ rho,
+                                                     uint8_t* __restrict__ ev, int64_t evlen)
 {
     __shared__ unsigned long long win[kWindow];
-    const int64_t n = P.cnt->n[S];
+    __shared__ int ncand;
+    const int64_t n = P.cnt->n[kElectron];
     const uint32_t step = uint32_t(P.cnt->step);
-    const int64_t per = ((n + gridDim.x - 1) / gridDim.x + 63) & ~int64_t(63);
-    const int64_t beg = int64_t(blockIdx.x) * per;
-    const int64_t end = beg + per < n ? beg + per : n;
+    int64_t beg, end;
+    block_chunk(n, beg, end);
+    if (beg >= end) return;
+
+    for (int k = threadIdx.x; k < kWindow; k += kAdvBlock) win[k] = 0ull;
+    if (threadIdx.x == 0) ncand = 0;
+    double f0;
+    const int wbase = cell_frac(P, sp.x[beg], f0) - kHalo;
+    __syncthreads();
+    const double* __restrict__ E = P.E;
+    uint32_t* __restrict__ cl = P.cand + beg;   // this block's candidate segment
+
+    for (int64_t i0 = beg; i0 < end; i0 += kAdvBlock) {
+        const int64_t i = i0 + threadIdx.x;
+        const bool act = i < end;
+        bool alive = false, cand = false;
+        int jn = 0;
+        int64_t an = 0;
+        if (act) {
+            double x = sp.x[i];
+            double vx = sp.vx[i];
+            const uint32_t id = sp.id[i];
+            double f;
+            const int j = cell_frac(P, x, f);
+            const double Ex = E[j] + f * (E[j + 1] - E[j]);
+            vx = vx + P.qmdt_e * Ex;
+            x = x + vx * P.dt;
+            uint8_t code = kEvNone;
+            alive = apply_boundary(P, x, code);
+            if (alive) {
+                const U4 w = philox10(id, step, 0u, kStreamElectronStep, P.key0, P.key1);
+                const double u0 = unif52(w.a, w.b);
+                if (u0 >= P.T_we) {
+                    alive = false;
+                    code = kEvWall;
+                } else {
+                    cand = u0 < P.P_null;
+                }
+            }
+            if (alive) {
+                sp.x[i] = x;
+                sp.vx[i] = vx;
+                double fn;
+                jn = cell_frac(P, x, fn);
+                an = frac_units(fn);
+            }
+            if (EV && !cand && int64_t(id) < evlen) ev[id] = code;
+        }
+        const int64_t hp = wave_append(act && !alive, &P.cnt->nh[kElectron]);
+        if (hp >= 0) {
+            if (hp < P.max_holes) P.holes[kElectron][hp] = uint32_t(i);
+            else set_err(P, kErrLosses);
+        }
+        {   // candidates: one LDS atomic per wave into the block's segment
+            const uint64_t m = __ballot(cand);
+            if (m != 0) {
+                const int leader = __ffsll((unsigned long long)m) - 1;
+                int base = 0;
+                if (lane_id() == leader) base = atomicAdd(&ncand, __popcll((unsigned long long)m));
+                base = __shfl(base, leader);
+                if (cand) cl[base + int(lanes_below(m))] = uint32_t(i);
+            }
+        }
+        deposit_wave(P, win, wbase, rho, alive, jn, an);
+    }
+    __syncthreads();
+    for (int k = threadIdx.x; k < kWindow; k += kAdvBlock) {
+        const unsigned long long v = win[k];
+        if (v != 0ull) {
+            const int node = wbase + k;
+            if (node >= 0 && node < P.nn) atomicAdd((unsigned long long*)&rho[node], v);
+        }
+    }
+    // phase 2: this block's collision candidates (their data is still hot)
+    const int nc = ncand;
+    for (int k0 = 0; k0 < nc; k0 += kAdvBlock) {
+        const int k = k0 + int(threadIdx.x);
+        collide_one<EV>(P, sp, ev, evlen, step, k < nc, k < nc ? cl[k] : 0u);
+    }
+}
+
+// -------------------------------------------------------------- ion advance
+// Ions on subcycle steps (dt_i = S dt): gather, push, boundary, radial sink,
+// charge exchange with a Maxwellian atom (null-collision bound Ng sigma g_cap,
+// accepted with g / g_cap, the ion takes the atom's velocity), deposit.
+template <bool EV>
+__global__ __launch_bounds__(kAdvBlock) void k_advance_i(Params P, Soa sp, int64_t* __restrict__ rho,
+                                                        uint8_t* __restrict__ ev, int64_t evlen)
+{
+    __shared__ unsigned long long win[kWindow];
+    const int64_t n = P.cnt->n[kIon];
+    const uint32_t step = uint32_t(P.cnt->step);
+    int64_t beg, end;
+    block_chunk(n, beg, end);
     if (beg >= end) return;
 
     for (int k = threadIdx.x; k < kWindow; k += kAdvBlock) win[k] = 0ull;
     double f0;
     const int wbase = cell_frac(P, sp.x[beg], f0) - kHalo;
     __syncthreads();
-
-    const double dts = S == kElectron ? P.dt : P.dti;
-    const double qmdt = S == kElectron ? P.qmdt_e : P.qmdt_i;
-    const double Tw = S == kElectron ? P.T_we : P.T_wi;
-    const uint32_t stream = S == kElectron ? kStreamElectronStep : kStreamIonStep;
     const double* __restrict__ E = P.E;
 
     for (int64_t i0 = beg; i0 < end; i0 += kAdvBlock) {
         const int64_t i = i0 + threadIdx.x;
         const bool act = i < end;
         bool alive = false;
-        bool born = false;
         int jn = 0;
         int64_t an = 0;
-        uint8_t code = kEvNone;
-        uint32_t id = 0;
-        double x = 0.0;
-        // birth record fields
-        double bve0 = 0, bve1 = 0, bve2 = 0, bvi0 = 0, bvi1 = 0, bvi2 = 0;
         if (act) {
-            x = sp.x[i];
+            double x = sp.x[i];
             double vx = sp.vx[i];
-            id = sp.id[i];
+            const uint32_t id = sp.id[i];
             double f;
             const int j = cell_frac(P, x, f);
             const double Ex = E[j] + f * (E[j + 1] - E[j]);
-            vx = vx + qmdt * Ex;
-            x = x + vx * dts;
-            alive = true;
-            if (P.periodic) {
-                if (x >= P.L) x -= P.L;
-                else if (x < 0.0) {
-                    x += P.L;
-                    if (x >= P.L) x = 0.0;
-                }
-                if (!(x >= 0.0 && x < P.L)) {
-                    set_err(P, kErrRange);
-                    x = 0.0;
-                }
-            } else if (!(x >= 0.0 && x < P.L)) {
-                if (!(x < 0.0 || x >= P.L)) set_err(P, kErrRange);
-                alive = false;
-                code = kEvAbsorb;
-            }
+            vx = vx + P.qmdt_i * Ex;
+            x = x + vx * P.dti;
+            uint8_t code = kEvNone;
+            alive = apply_boundary(P, x, code);
             if (alive) {
-                const U4 w = philox10(id, step, 0u, stream, P.key0, P.key1);
+                const U4 w = philox10(id, step, 0u, kStreamIonStep, P.key0, P.key1);
                 const double u0 = unif52(w.a, w.b);
                 const double u1 = unif52(w.c, w.d);
-                if (u0 >= Tw) {
+                if (u0 >= P.T_wi) {
                     alive = false;
                     code = kEvWall;
-                } else if (S == kElectron && u0 < P.P_null) {
+                } else if (u0 < P.P_cx) {
                     double vy = sp.vy[i], vz = sp.vz[i];
-                    const double v2 = (vx * vx + vy * vy) + vz * vz;
-                    const double eps = P.c_eps * v2;
-                    const double v = sqrt(v2);
-                    if (eps > P.eps_cap) set_err(P, kErrECap);
-                    const double s_el = sigma_elastic(P, eps);
-                    const double s_ex = sigma_inelastic(eps, P.ex_U, P.sx4);
-                    const double s_iz = sigma_inelastic(eps, P.iz_U, P.si4);
-                    const double c1 = s_el * v * P.Ng;
-                    const double c2 = c1 + s_ex * v * P.Ng;
-                    const double c3 = c2 + s_iz * v * P.Ng;
-                    if (c3 > P.nu_max) set_err(P, kErrNuMax);
-                    const double R = u1 * P.nu_max;
-                    WordStream ws(id, step, stream, P.key0, P.key1);
-                    double nx, ny, nz;
-                    if (R < c1) {
-                        code = kEvElastic;
-                        isotropic(ws, nx, ny, nz);
-                        const double cosx = ((vx * nx + vy * ny) + vz * nz) / v;
-                        const double fac = 1.0 - P.mr2 * (1.0 - cosx);
-                        const double vn = v * sqrt(fac);
-                        vx = vn * nx;
-                        vy = vn * ny;
-                        vz = vn * nz;
-                    } else if (R < c2) {
-                        code = kEvExcite;
-                        isotropic(ws, nx, ny, nz);
-                        const double vn = sqrt((eps - P.ex_U) / P.c_eps);
-                        vx = vn * nx;
-                        vy = vn * ny;
-                        vz = vn * nz;
-                    } else if (R < c3) {
-                        code = kEvIonize;
-                        const double us = ws.u();
-                        const double er = eps - P.iz_U;
-                        const double ej =
-                            P.share_equal ? 0.5 * er : P.opb_w * tan(us * atan(er / (2.0 * P.opb_w)));
-                        const double sc = er - ej;
-                        double mx, my, mz, g0, g1, g2;
-                        isotropic(ws, nx, ny, nz);
-                        isotropic(ws, mx, my, mz);
-                        normal3(ws, g0, g1, g2);
-                        const double vs = sqrt(sc / P.c_eps);
-                        const double ve = sqrt(ej / P.c_eps);
-                        vx = vs * nx;
-                        vy = vs * ny;
-                        vz = vs * nz;
-                        bve0 = ve * mx;
-                        bve1 = ve * my;
-                        bve2 = ve * mz;
-                        bvi0 = P.sig_a * g0;
-                        bvi1 = P.sig_a * g1;
-                        bvi2 = P.sig_a * g2;
-                        born = true;
-                    } else {
-                        code = kEvNull;
-                    }
-                    sp.vy[i] = vy;
-                    sp.vz[i] = vz;
-                } else if (S == kIon && u0 < P.P_cx) {
-                    double vy = sp.vy[i], vz = sp.vz[i];
-                    WordStream ws(id, step, stream, P.key0, P.key1);
+                    WordStream ws(id, step, kStreamIonStep, P.key0, P.key1);
                     double g0, g1, g2;
                     normal3(ws, g0, g1, g2);
                     const double ax = P.sig_a * g0, ay = P.sig_a * g1, az = P.sig_a * g2;
@@ -248,31 +391,12 @@ __global__ __launch_bounds__(kAdvBlock) void k_advance(Params P, Soa sp, int64_t
                 jn = cell_frac(P, x, fn);
                 an = frac_units(fn);
             }
-            if (ev != nullptr && int64_t(id) < evlen) ev[id] = code;
+            if (EV && int64_t(id) < evlen) ev[id] = code;
         }
-        // losses: slot indices for the compaction
-        const int64_t hp = wave_append(act && !alive, &P.cnt->nh[S]);
+        const int64_t hp = wave_append(act && !alive, &P.cnt->nh[kIon]);
         if (hp >= 0) {
-            if (hp < P.max_holes) P.holes[S][hp] = uint32_t(i);
+            if (hp < P.max_holes) P.holes[kIon][hp] = uint32_t(i);
             else set_err(P, kErrLosses);
-        }
-        // ionization products
-        if (S == kElectron) {
-            const int64_t bp = wave_append(born, &P.cnt->nb);
-            if (bp >= 0) {
-                if (bp < P.max_births) {
-                    Birth b;
-                    b.pid = id;
-                    b.pad = 0;
-                    b.x = x;
-                    b.ve[0] = bve0; b.ve[1] = bve1; b.ve[2] = bve2;
-                    b.vi[0] = bvi0; b.vi[1] = bvi1; b.vi[2] = bvi2;
-                    P.births[bp] = b;
-                    atomicAdd((unsigned long long*)&P.iz[jn], 1ull);
-                } else {
-                    set_err(P, kErrBirths);
-                }
-            }
         }
         deposit_wave(P, win, wbase, rho, alive, jn, an);
     }
@@ -446,100 +570,242 @@ __global__ __launch_bounds__(kOneBlock) void k_field(Params P, const int64_t* rh
 }
 
 // ------------------------------------------------------------------ finish
-// Single workgroup: fill loss holes from the array tail, append ionization
-// products ordered by parent id (new ids = next id + rank), deposit them,
-// update counters, solve the field, clear the next charge buffers.
+// Single workgroup, once per step:
+//  1. field solve E^{n+1} from the advance kernels' charges;
+//  2. ionization kinematics (energy sharing of eps - U_iz, isotropic scattered
+//     and ejected electrons, Maxwellian ion) from the parent's word stream;
+//     the parent's velocity is updated in place, the products' charge is
+//     deposited;
+//  3. loss holes filled from the array tail (both species);
+//  4. products appended in parent-id order (new id = next id + rank);
+//  5. counters, clearing of the next charge buffers.
+constexpr int kListMax = 2048;    // per-step lists handled in LDS (larger: global scratch)
+constexpr int kBirthRegs = kListMax / kOneBlock;
+
+// ionization products of birth b: scattered velocity of the parent, ejected
+// electron and new ion velocities (same draw order as every other consumer of
+// the (id, step) word stream: split, two directions, three normals)
+__device__ __forceinline__ void ionize(const Params& P, const Birth& b, uint32_t step, double vs[3],
+                                       double ve[3], double vi[3])
+{
+    WordStream ws(b.pid, step, kStreamElectronStep, P.key0, P.key1);
+    const double us = ws.u();
+    const double er = b.eps - P.iz_U;
+    const double ej = P.share_equal ? 0.5 * er : P.opb_w * tan(us * atan(er / (2.0 * P.opb_w)));
+    const double sc = er - ej;
+    double nx, ny, nz, mx, my, mz, g0, g1, g2;
+    isotropic(ws, nx, ny, nz);
+    isotropic(ws, mx, my, mz);
+    normal3(ws, g0, g1, g2);
+    const double a = sqrt(sc / P.c_eps);
+    const double c = sqrt(ej / P.c_eps);
+    vs[0] = a * nx; vs[1] = a * ny; vs[2] = a * nz;
+    ve[0] = c * mx; ve[1] = c * my; ve[2] = c * mz;
+    vi[0] = P.sig_a * g0; vi[1] = P.sig_a * g1; vi[2] = P.sig_a * g2;
+}
+
+__device__ __forceinline__ void deposit_global(const Params& P, int64_t* rho, double x)
+{
+    double f;
+    const int j = cell_frac(P, x, f);
+    const int64_t a = frac_units(f);
+    int j1 = j + 1;
+    if (P.periodic && j1 == P.nc) j1 = 0;
+    atomicAdd((unsigned long long*)&rho[j], (unsigned long long)(kUnit - a));
+    atomicAdd((unsigned long long*)&rho[j1], (unsigned long long)a);
+}
+
+__device__ __forceinline__ void move_particle(const Soa& sp, uint32_t dst, uint32_t src)
+{
+    sp.x[dst] = sp.x[src];
+    sp.vx[dst] = sp.vx[src];
+    sp.vy[dst] = sp.vy[src];
+    sp.vz[dst] = sp.vz[src];
+    sp.id[dst] = sp.id[src];
+}
+
 __global__ __launch_bounds__(kOneBlock) void k_finish(Params P, Soa se, Soa si, int64_t* rho_e,
                                                       int64_t* rho_i, int64_t* zero_a, int64_t* zero_b)
 {
-    __shared__ int64_t sh_n[2];
-    __shared__ unsigned int sh_c[2];
+    __shared__ int64_t sN[2], sNH[2], sID[2], sNB, sStep;
+    __shared__ uint32_t sPid[kListMax];
+    __shared__ uint32_t sFlag[2][kListMax / 32];
+    __shared__ uint32_t sL1[2][kListMax], sL2[2][kListMax];
+    __shared__ unsigned int sC[4];
     const int tid = threadIdx.x;
     const int T = blockDim.x;
     Counters* cnt = P.cnt;
-    for (int s = 0; s < 2; ++s) {
-        const Soa sp = s == 0 ? se : si;
-        const int64_t N = cnt->n[s];
-        int64_t nh = cnt->nh[s];
-        if (nh > P.max_holes) nh = 0;   // overflow already flagged; state is invalid
-        const int64_t Np = N - nh;
-        if (tid == 0) { sh_n[s] = Np; sh_c[0] = 0u; sh_c[1] = 0u; }
-        if (nh == 0) continue;
-        const int64_t words = (nh + 31) >> 5;
-        for (int64_t k = tid; k < words; k += T) P.bitmap[k] = 0u;
-        __syncthreads();
-        for (int64_t k = tid; k < nh; k += T) {
-            const int64_t h = P.holes[s][k];
-            if (h >= Np) atomicOr(&P.bitmap[(h - Np) >> 5], 1u << ((h - Np) & 31));
-        }
-        __syncthreads();
-        uint32_t* L1 = P.lists;
-        uint32_t* L2 = P.lists + P.max_holes;
-        for (int64_t k = tid; k < nh; k += T) {
-            const int64_t h = P.holes[s][k];
-            if (h < Np) L1[atomicAdd(&sh_c[0], 1u)] = uint32_t(h);
-            const int64_t t = Np + k;
-            if (!((P.bitmap[k >> 5] >> (k & 31)) & 1u)) L2[atomicAdd(&sh_c[1], 1u)] = uint32_t(t);
-        }
-        __syncthreads();
-        const unsigned int m = sh_c[0];
-        for (unsigned int k = tid; k < m; k += T) {
-            const uint32_t dst = L1[k], src = L2[k];
-            sp.x[dst] = sp.x[src];
-            sp.vx[dst] = sp.vx[src];
-            sp.vy[dst] = sp.vy[src];
-            sp.vz[dst] = sp.vz[src];
-            sp.id[dst] = sp.id[src];
-        }
-        __syncthreads();
-        if (tid == 0) { sh_c[0] = 0u; sh_c[1] = 0u; }
-        __syncthreads();
-    }
-    __syncthreads();
-    const int64_t ne = sh_n[0], ni = sh_n[1];
-    int64_t nb = cnt->nb;
-    if (nb > P.max_births) nb = P.max_births;
-    if (ne + nb > P.cap || ni + nb > P.cap) {
-        if (tid == 0) set_err(P, kErrCapacity);
-        nb = 0;
-    }
-    const int64_t ide = cnt->next_id[0], idi = cnt->next_id[1];
-    for (int64_t k = tid; k < nb; k += T) {
-        const Birth b = P.births[k];
-        int64_t r = 0;
-        for (int64_t m = 0; m < nb; ++m) r += P.births[m].pid < b.pid ? 1 : 0;
-        const int64_t pe = ne + r, pi = ni + r;
-        se.x[pe] = b.x; se.vx[pe] = b.ve[0]; se.vy[pe] = b.ve[1]; se.vz[pe] = b.ve[2];
-        se.id[pe] = uint32_t(ide + r);
-        si.x[pi] = b.x; si.vx[pi] = b.vi[0]; si.vy[pi] = b.vi[1]; si.vz[pi] = b.vi[2];
-        si.id[pi] = uint32_t(idi + r);
-        double f;
-        const int j = cell_frac(P, b.x, f);
-        const int64_t a = frac_units(f);
-        int j1 = j + 1;
-        if (P.periodic && j1 == P.nc) j1 = 0;
-        atomicAdd((unsigned long long*)&rho_e[j], (unsigned long long)(kUnit - a));
-        atomicAdd((unsigned long long*)&rho_e[j1], (unsigned long long)a);
-        atomicAdd((unsigned long long*)&rho_i[j], (unsigned long long)(kUnit - a));
-        atomicAdd((unsigned long long*)&rho_i[j1], (unsigned long long)a);
-    }
-    __threadfence();
-    __syncthreads();
     if (tid == 0) {
-        cnt->n[0] = ne + nb;
-        cnt->n[1] = ni + nb;
-        cnt->next_id[0] = ide + nb;
-        cnt->next_id[1] = idi + nb;
-        if (ide + nb > 0xFFFFFFFFll || idi + nb > 0xFFFFFFFFll) set_err(P, kErrIds);
-        cnt->nb = 0;
-        cnt->nh[0] = 0;
-        cnt->nh[1] = 0;
+        sN[0] = cnt->n[0];
+        sN[1] = cnt->n[1];
+        sNH[0] = cnt->nh[0];
+        sNH[1] = cnt->nh[1];
+        sID[0] = cnt->next_id[0];
+        sID[1] = cnt->next_id[1];
+        sNB = cnt->nb;
+        sStep = cnt->step;
+        sC[0] = sC[1] = sC[2] = sC[3] = 0u;
     }
+    // 1. field E^{n+1}.  An ionization adds an electron and an ion at the same
+    //    position, so the net charge -- and the field -- do not depend on this
+    //    step's products: the solve needs only the charges deposited by the
+    //    advance kernels and runs first.
     if (P.poisson) {
         field_block(P, rho_e, rho_i, P.E, nullptr, true);
     } else {
         const double e0 = P.periodic ? -P.E0 : -(P.V / P.L);
         for (int j = tid; j <= P.nn; j += T) P.E[j] = e0;
+    }
+    __syncthreads();
+    const uint32_t step = uint32_t(sStep);
+    int64_t nb = sNB < P.max_births ? sNB : P.max_births;
+    int64_t nh[2], Np[2];
+    bool lds[2];
+    for (int s = 0; s < 2; ++s) {
+        nh[s] = sNH[s] <= P.max_holes ? sNH[s] : 0;   // overflow already flagged
+        Np[s] = sN[s] - nh[s];
+        lds[s] = nh[s] <= kListMax;
+    }
+    if (Np[0] + nb > P.cap || Np[1] + nb > P.cap) {
+        if (tid == 0) set_err(P, kErrCapacity);
+        nb = 0;
+    }
+    const bool bfast = nb <= kListMax;
+
+    // 2. births: parent update, products' charge; product velocities kept in
+    //    registers (lists longer than kListMax recompute them in step 3)
+    double bve[kBirthRegs][3], bvi[kBirthRegs][3], bx[kBirthRegs];
+    uint32_t bpid[kBirthRegs];
+#pragma unroll
+    for (int m = 0; m < kBirthRegs; ++m) {
+        bpid[m] = 0;
+        bx[m] = 0.0;
+        for (int q = 0; q < 3; ++q) { bve[m][q] = 0.0; bvi[m][q] = 0.0; }
+    }
+    if (bfast) {
+#pragma unroll
+        for (int m = 0; m < kBirthRegs; ++m) {
+            const int64_t k = tid + int64_t(m) * T;
+            if (k < nb) {
+                const Birth b = P.births[k];
+                double vs[3];
+                ionize(P, b, step, vs, bve[m], bvi[m]);
+                se.vx[b.slot] = vs[0];
+                se.vy[b.slot] = vs[1];
+                se.vz[b.slot] = vs[2];
+                deposit_global(P, rho_e, b.x);
+                deposit_global(P, rho_i, b.x);
+                sPid[k] = b.pid;
+                bpid[m] = b.pid;
+                bx[m] = b.x;
+            }
+        }
+    } else {
+        for (int64_t k = tid; k < nb; k += T) {
+            const Birth b = P.births[k];
+            double vs[3], ve[3], vi[3];
+            ionize(P, b, step, vs, ve, vi);
+            se.vx[b.slot] = vs[0];
+            se.vy[b.slot] = vs[1];
+            se.vz[b.slot] = vs[2];
+            deposit_global(P, rho_e, b.x);
+            deposit_global(P, rho_i, b.x);
+        }
+    }
+    // 3. hole filling from the tail [Np, N): small lists in LDS
+    for (int s = 0; s < 2; ++s)
+        if (lds[s])
+            for (int k = tid; k < kListMax / 32; k += T) sFlag[s][k] = 0u;
+    __syncthreads();
+    for (int s = 0; s < 2; ++s) {
+        if (!lds[s] || nh[s] == 0) continue;
+        for (int64_t k = tid; k < nh[s]; k += T) {
+            const int64_t h = P.holes[s][k];
+            if (h >= Np[s]) atomicOr(&sFlag[s][(h - Np[s]) >> 5], 1u << ((h - Np[s]) & 31));
+            else sL1[s][atomicAdd(&sC[2 * s], 1u)] = uint32_t(h);
+        }
+    }
+    __syncthreads();
+    for (int s = 0; s < 2; ++s) {
+        if (!lds[s] || nh[s] == 0) continue;
+        for (int64_t k = tid; k < nh[s]; k += T)
+            if (!((sFlag[s][k >> 5] >> (k & 31)) & 1u)) sL2[s][atomicAdd(&sC[2 * s + 1], 1u)] = uint32_t(Np[s] + k);
+    }
+    __syncthreads();
+    for (int s = 0; s < 2; ++s) {
+        if (!lds[s] || nh[s] == 0) continue;
+        const Soa sp = s == 0 ? se : si;
+        for (unsigned int k = tid; k < sC[2 * s]; k += T) move_particle(sp, sL1[s][k], sL2[s][k]);
+    }
+    // large hole lists: the same algorithm on global scratch, one species at a time
+    for (int s = 0; s < 2; ++s) {
+        if (lds[s] || nh[s] == 0) continue;
+        const Soa sp = s == 0 ? se : si;
+        const int64_t words = (nh[s] + 31) >> 5;
+        if (tid == 0) { sC[0] = 0u; sC[1] = 0u; }
+        for (int64_t k = tid; k < words; k += T) P.bitmap[k] = 0u;
+        __threadfence_block();
+        __syncthreads();
+        for (int64_t k = tid; k < nh[s]; k += T) {
+            const int64_t h = P.holes[s][k];
+            if (h >= Np[s]) atomicOr(&P.bitmap[(h - Np[s]) >> 5], 1u << ((h - Np[s]) & 31));
+        }
+        __threadfence_block();
+        __syncthreads();
+        uint32_t* L1 = P.lists;
+        uint32_t* L2 = P.lists + P.max_holes;
+        for (int64_t k = tid; k < nh[s]; k += T) {
+            const int64_t h = P.holes[s][k];
+            if (h < Np[s]) L1[atomicAdd(&sC[0], 1u)] = uint32_t(h);
+            if (!((P.bitmap[k >> 5] >> (k & 31)) & 1u)) L2[atomicAdd(&sC[1], 1u)] = uint32_t(Np[s] + k);
+        }
+        __threadfence_block();
+        __syncthreads();
+        for (unsigned int k = tid; k < sC[0]; k += T) move_particle(sp, L1[k], L2[k]);
+        __threadfence_block();
+        __syncthreads();
+    }
+    __syncthreads();
+    // 4. append products at Np + rank (rank of the parent id among this step's)
+    if (bfast) {
+#pragma unroll
+        for (int m = 0; m < kBirthRegs; ++m) {
+            const int64_t k = tid + int64_t(m) * T;
+            if (k < nb) {
+                int64_t r = 0;
+                for (int64_t q = 0; q < nb; ++q) r += sPid[q] < bpid[m] ? 1 : 0;
+                const int64_t pe = Np[0] + r, pi = Np[1] + r;
+                se.x[pe] = bx[m]; se.vx[pe] = bve[m][0]; se.vy[pe] = bve[m][1]; se.vz[pe] = bve[m][2];
+                se.id[pe] = uint32_t(sID[0] + r);
+                si.x[pi] = bx[m]; si.vx[pi] = bvi[m][0]; si.vy[pi] = bvi[m][1]; si.vz[pi] = bvi[m][2];
+                si.id[pi] = uint32_t(sID[1] + r);
+            }
+        }
+    } else {
+        for (int64_t k = tid; k < nb; k += T) {
+            const Birth b = P.births[k];
+            double vs[3], ve[3], vi[3];
+            ionize(P, b, step, vs, ve, vi);
+            int64_t r = 0;
+            for (int64_t q = 0; q < nb; ++q) r += P.births[q].pid < b.pid ? 1 : 0;
+            const int64_t pe = Np[0] + r, pi = Np[1] + r;
+            se.x[pe] = b.x; se.vx[pe] = ve[0]; se.vy[pe] = ve[1]; se.vz[pe] = ve[2];
+            se.id[pe] = uint32_t(sID[0] + r);
+            si.x[pi] = b.x; si.vx[pi] = vi[0]; si.vy[pi] = vi[1]; si.vz[pi] = vi[2];
+            si.id[pi] = uint32_t(sID[1] + r);
+        }
+    }
+    __threadfence();
+    __syncthreads();
+    if (tid == 0) {
+        cnt->n[0] = Np[0] + nb;
+        cnt->n[1] = Np[1] + nb;
+        cnt->next_id[0] = sID[0] + nb;
+        cnt->next_id[1] = sID[1] + nb;
+        if (sID[0] + nb > 0xFFFFFFFFll || sID[1] + nb > 0xFFFFFFFFll) set_err(P, kErrIds);
+        cnt->nb = 0;
+        cnt->nh[0] = 0;
+        cnt->nh[1] = 0;
     }
     for (int j = tid; j < P.nn; j += T) {
         if (zero_a) zero_a[j] = 0;
@@ -662,31 +928,68 @@ __global__ void k_reset_iz(Params P)
 }
 
 // -------------------------------------------------------------------- sort
-// Counting sort by cell: histogram, exclusive scan, scatter.  The order inside
-// a cell is arbitrary; nothing downstream depends on array order.
+// Counting sort by cell (histogram, exclusive scan, scatter).  Blocks take
+// the same contiguous chunks as the particle kernels; a chunk of an almost
+// sorted array covers few cells, so counts and ranks are kept in an LDS
+// window of cells and each (block, cell) reserves its output range with one
+// global atomic.  The order inside a cell is arbitrary; nothing downstream
+// depends on array order.
+
+// lanes of a wave sharing a cell (up to two distinct cells) add their count
+// to the window with one LDS atomic; others add one each.  Out-of-window
+// lanes go to the global histogram when `glob` is set.
+__device__ __forceinline__ void count_wave(int* cw, int wbase, int32_t* glob, bool act, int c)
+{
+    bool pend = act;
+#pragma unroll
+    for (int it = 0; it < 2; ++it) {
+        const uint64_t m = __ballot(pend);
+        if (m == 0) return;
+        const int leader = __ffsll((unsigned long long)m) - 1;
+        const int cr = __builtin_amdgcn_readlane(c, leader);
+        const bool mine = pend && c == cr;
+        const uint64_t mm = __ballot(mine);
+        if (lane_id() == leader) {
+            const int li = cr - wbase;
+            const int k = __popcll((unsigned long long)mm);
+            if (li >= 0 && li < kWindow) atomicAdd(&cw[li], k);
+            else if (glob) atomicAdd(&glob[cr], k);
+        }
+        pend = pend && !mine;
+    }
+    if (pend) {
+        const int li = c - wbase;
+        if (li >= 0 && li < kWindow) atomicAdd(&cw[li], 1);
+        else if (glob) atomicAdd(&glob[c], 1);
+    }
+}
+
 __global__ __launch_bounds__(256) void k_sort_count(Params P, Soa sp, int S)
 {
+    __shared__ int cw[kWindow];
     const int64_t n = P.cnt->n[S];
-    for (int64_t i0 = int64_t(blockIdx.x) * blockDim.x; i0 < n; i0 += int64_t(gridDim.x) * blockDim.x) {
+    int64_t beg, end;
+    block_chunk(n, beg, end);
+    if (beg >= end) return;
+    for (int k = threadIdx.x; k < kWindow; k += blockDim.x) cw[k] = 0;
+    double f0;
+    const int wbase = cell_frac(P, sp.x[beg], f0) - kHalo;
+    __syncthreads();
+    for (int64_t i0 = beg; i0 < end; i0 += blockDim.x) {
         const int64_t i = i0 + threadIdx.x;
-        const bool act = i < n;
+        const bool act = i < end;
         int c = 0;
         if (act) {
             double f;
             c = cell_frac(P, sp.x[i], f);
         }
-        bool pend = act;
-        for (int it = 0; it < 2; ++it) {
-            const uint64_t m = __ballot(pend);
-            if (m == 0) break;
-            const int leader = __ffsll((unsigned long long)m) - 1;
-            const int cr = __builtin_amdgcn_readlane(c, leader);
-            const bool mine = pend && c == cr;
-            const uint64_t mm = __ballot(mine);
-            if (lane_id() == leader) atomicAdd(&P.sort_cnt[cr], __popcll((unsigned long long)mm));
-            pend = pend && !mine;
-        }
-        if (pend) atomicAdd(&P.sort_cnt[c], 1);
+        count_wave(cw, wbase, P.sort_cnt, act, c);
+    }
+    __syncthreads();
+    for (int k = threadIdx.x; k < kWindow; k += blockDim.x) {
+        const int v = cw[k];
+        const int c = wbase + k;
+        if (v != 0 && c >= 0 && c < P.nc) atomicAdd(&P.sort_cnt[c], v);
     }
 }
 
@@ -714,17 +1017,48 @@ __global__ __launch_bounds__(kOneBlock) void k_sort_scan(Params P)
 
 __global__ __launch_bounds__(256) void k_sort_scatter(Params P, Soa src, Soa dst, int S)
 {
+    __shared__ int cw[kWindow];
+    __shared__ int bw[kWindow];
     const int64_t n = P.cnt->n[S];
-    for (int64_t i0 = int64_t(blockIdx.x) * blockDim.x; i0 < n; i0 += int64_t(gridDim.x) * blockDim.x) {
+    int64_t beg, end;
+    block_chunk(n, beg, end);
+    if (beg >= end) return;
+    for (int k = threadIdx.x; k < kWindow; k += blockDim.x) cw[k] = 0;
+    double f0;
+    const int wbase = cell_frac(P, src.x[beg], f0) - kHalo;
+    __syncthreads();
+    // pass 1: in-window counts of this chunk
+    for (int64_t i0 = beg; i0 < end; i0 += blockDim.x) {
         const int64_t i = i0 + threadIdx.x;
-        const bool act = i < n;
+        const bool act = i < end;
         int c = 0;
         if (act) {
             double f;
             c = cell_frac(P, src.x[i], f);
         }
-        int64_t pos = -1;
+        count_wave(cw, wbase, nullptr, act, c);
+    }
+    __syncthreads();
+    // one reservation per (block, cell)
+    for (int k = threadIdx.x; k < kWindow; k += blockDim.x) {
+        const int v = cw[k];
+        if (v != 0) bw[k] = atomicAdd(&P.sort_off[wbase + k], v);
+        cw[k] = 0;
+    }
+    __syncthreads();
+    // pass 2: ranks inside the reserved ranges; out-of-window particles take
+    // single global slots
+    for (int64_t i0 = beg; i0 < end; i0 += blockDim.x) {
+        const int64_t i = i0 + threadIdx.x;
+        const bool act = i < end;
+        int c = 0;
+        if (act) {
+            double f;
+            c = cell_frac(P, src.x[i], f);
+        }
+        int pos = 0;
         bool pend = act;
+#pragma unroll
         for (int it = 0; it < 2; ++it) {
             const uint64_t m = __ballot(pend);
             if (m == 0) break;
@@ -733,12 +1067,21 @@ __global__ __launch_bounds__(256) void k_sort_scatter(Params P, Soa src, Soa dst
             const bool mine = pend && c == cr;
             const uint64_t mm = __ballot(mine);
             int base = 0;
-            if (lane_id() == leader) base = atomicAdd(&P.sort_off[cr], __popcll((unsigned long long)mm));
+            if (lane_id() == leader) {
+                const int li = cr - wbase;
+                const int k = __popcll((unsigned long long)mm);
+                if (li >= 0 && li < kWindow) base = bw[li] + atomicAdd(&cw[li], k);
+                else base = atomicAdd(&P.sort_off[cr], k);
+            }
             base = __shfl(base, leader);
             if (mine) pos = base + int(lanes_below(mm));
             pend = pend && !mine;
         }
-        if (pend) pos = atomicAdd(&P.sort_off[c], 1);
+        if (pend) {
+            const int li = c - wbase;
+            if (li >= 0 && li < kWindow) pos = bw[li] + atomicAdd(&cw[li], 1);
+            else pos = atomicAdd(&P.sort_off[c], 1);
+        }
         if (act) {
             dst.x[pos] = src.x[i];
             dst.vx[pos] = src.vx[i];
@@ -766,10 +1109,14 @@ static int grid_for(int64_t n, int block, int maxg)
 hipError_t advance(const Params& P, int species, const Soa& sp, int64_t* rho, uint8_t* ev, int64_t evlen,
                    int grid, hipStream_t st)
 {
-    if (species == kElectron)
-        hipLaunchKernelGGL(k_advance<kElectron>, dim3(grid), dim3(kAdvBlock), 0, st, P, sp, rho, ev, evlen);
-    else
-        hipLaunchKernelGGL(k_advance<kIon>, dim3(grid), dim3(kAdvBlock), 0, st, P, sp, rho, ev, evlen);
+    const bool e = ev != nullptr;
+    if (species == kElectron) {
+        if (e) hipLaunchKernelGGL(k_push_e<true>, dim3(grid), dim3(kAdvBlock), 0, st, P, sp, rho, ev, evlen);
+        else hipLaunchKernelGGL(k_push_e<false>, dim3(grid), dim3(kAdvBlock), 0, st, P, sp, rho, ev, evlen);
+    } else {
+        if (e) hipLaunchKernelGGL(k_advance_i<true>, dim3(grid), dim3(kAdvBlock), 0, st, P, sp, rho, ev, evlen);
+        else hipLaunchKernelGGL(k_advance_i<false>, dim3(grid), dim3(kAdvBlock), 0, st, P, sp, rho, ev, evlen);
+    }
     return hipGetLastError();
 }
 
