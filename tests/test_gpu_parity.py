@@ -200,3 +200,29 @@ def test_step_parity_long_loss_and_birth_lists(torch_cuda):
     tot = _run_shared_state(torch, cfg, steps=2, setup=setup)
     assert tot[3] > 2 * 2048, tot      # ionizations over the two steps
     assert tot[4] > 2 * 2048, tot      # radial losses
+
+
+# ---------------------------------------------------------------- moments
+def test_moments_bitwise(torch_cuda):
+    # cell moments (counts, energy / flux sums, EEPF histogram, ionization
+    # counts) of the same state are integers: identical on both sides
+    cfg = W.tiny("periodic", n_cells=101, L=0.0101, V=0.0101 * 6.0e3, ppc=60, Te0_eV=8.0,
+                 nu_w=5e7, eps_cap=100.0, sort_interval=3)
+    col = _column(cfg)
+    orc = Oracle(cfg, init=False)
+    col.step(25)
+    col.moments(cells_per_group=4, reset_iz=True)
+    for k in range(3):
+        copy_gpu_to_oracle(col, orc)
+        orc.moments(reset_iz=True)
+        col.step(1)
+        orc.step(1)
+        for cpg in (1, 4, 101):
+            g = col.moments(cells_per_group=cpg).cpu().numpy()
+            o = orc.moments(cells_per_group=cpg)
+            nc = cfg["n_cells"]
+            assert np.array_equal(g[:6 * nc], o[:6 * nc])
+            assert np.array_equal(g[7 * nc:], o[7 * nc:])
+            assert np.array_equal(g[6 * nc:7 * nc], o[6 * nc:7 * nc])
+        col.moments(cells_per_group=1, reset_iz=True)
+    assert g[:nc].sum() == col.counts()["n"][0]
