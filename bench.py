@@ -37,10 +37,14 @@ WORKLOADS = {
 }
 
 
-def electron_bytes_per_step(p_null: float) -> float:
+def electron_bytes_per_step(p_null: float, fp32: bool = False) -> float:
     """Algorithmic HBM bytes per electron per step of the electron advance
-    kernel: read x, vx (FP64) and id (u32), write x, vx; collision candidates
-    (a fraction p_null) also list their slot (u32) and read vy, vz."""
+    kernel.  FP64: read x, vx and id (u32), write x, vx; candidates (a
+    fraction p_null) also list their slot (u32) and read vy, vz.  FP32: read
+    cell, offset, vx, id, write cell, offset, vx (4 B each); candidates list
+    their slot and read vy, vz (4 B each)."""
+    if fp32:
+        return 16 + 12 + p_null * (4 + 8)
     return 8 + 8 + 4 + 8 + 8 + p_null * (4 + 16)
 
 
@@ -60,32 +64,19 @@ def cpu_baseline(cfg: dict, steps: int) -> dict:
                       f"oracle ({dt:.1f} s)"}
 
 
-def main() -> int:
-    ap = argparse.ArgumentParser()
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=2000)
-    ap.add_argument("--warmup", type=int, default=200)
-    ap.add_argument("--workload", default="column_20cm", choices=sorted(WORKLOADS))
-    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
-    ap.add_argument("--cpu-steps", type=int, default=0, help="oracle sample length (0 = auto)")
-    args = ap.parse_args()
-    if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on exactly one GPU (no sharding or "
-                                   "collectives); run with --gpus 1"}))
-        return 2
-
+def measure(cfg: dict, args, tag: str) -> dict:
+    """Graph-replayed timed window (throughput) then an eager event-timed
+    window of the same length (electron push kernel duration)."""
     import torch
     from paper_2202_03215_amd.column import Column
 
-    cfg = WORKLOADS[args.workload]()
-    print(f"[bench] workload {args.workload}: init", file=sys.stderr, flush=True)
+    print(f"[bench] {tag}: init", file=sys.stderr, flush=True)
     col = Column(cfg)
     S = int(cfg["ion_subcycle"])
     col.step(args.warmup)
     col.sync()
     c0 = col.counts()
-    print(f"[bench] warmup {args.warmup} done, n = {c0['n']}", file=sys.stderr, flush=True)
-    # timed window: graph-replayed steps
+    print(f"[bench] {tag}: warmup {args.warmup} done, n = {c0['n']}", file=sys.stderr, flush=True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     col.step(args.steps)
@@ -98,12 +89,10 @@ def main() -> int:
     ion_steps = sum(1 for k in range(step0, step0 + args.steps) if k % S == 0)
     ne_avg = 0.5 * (c0["n"][0] + c1["n"][0])
     ni_avg = 0.5 * (c0["n"][1] + c1["n"][1])
-    psteps = ne_avg * args.steps + ni_avg * ion_steps
-    value = psteps / elapsed
-
-    # second timed window of the same length with HIP events around every
-    # electron-advance launch on the column's stream (eager launches: events
-    # recorded by graph nodes carry no readable time on this runtime)
+    value = (ne_avg * args.steps + ni_avg * ion_steps) / elapsed
+    # second timed window with HIP events around every electron-advance
+    # launch on the column's stream (eager launches: events recorded by
+    # graph nodes carry no readable time on this runtime)
     col.timer_enable(args.steps)
     torch.cuda.synchronize()
     t2 = time.perf_counter()
@@ -115,15 +104,47 @@ def main() -> int:
     c2 = col.counts()
     col.sync()
     ne_avg2 = 0.5 * (c1["n"][0] + c2["n"][0])
-
-    # roofline of the electron advance kernel
-    p_null = float(col.sizes.p_null)
-    bytes_per_launch = ne_avg2 * electron_bytes_per_step(p_null)
+    fp32 = cfg.get("precision", "fp64") == "fp32"
+    bytes_per_launch = ne_avg2 * electron_bytes_per_step(float(col.sizes.p_null), fp32)
     avg_s = ker_ms * 1e-3 / max(launches, 1)
     achieved = bytes_per_launch / avg_s / 1e9
-    print(f"[bench] {args.steps} steps in {elapsed:.3f} s (graphs), {t3 - t2:.3f} s (eager, timed); "
-          f"advance kernel avg {avg_s * 1e6:.2f} us over {launches} launches",
+    print(f"[bench] {tag}: {args.steps} steps in {elapsed:.3f} s (graphs), {t3 - t2:.3f} s (eager, "
+          f"timed); push kernel avg {avg_s * 1e6:.2f} us over {launches} launches",
           file=sys.stderr, flush=True)
+    del col
+    torch.cuda.empty_cache()
+    return {"value": value, "elapsed": elapsed, "ne": ne_avg, "ni": ni_avg,
+            "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                         "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                         "kernel": "k_push_e32" if fp32 else "k_push_e",
+                         "avg_us": avg_s * 1e6, "launches": launches,
+                         "bytes_per_launch": bytes_per_launch,
+                         "window": "eager timed window of the same length after the graph window",
+                         "ms_per_step_eager": (t3 - t2) * 1e3 / args.steps}}
+
+
+def main() -> int:
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=2000)
+    ap.add_argument("--warmup", type=int, default=200)
+    ap.add_argument("--workload", default="column_20cm", choices=sorted(WORKLOADS))
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--cpu-steps", type=int, default=0, help="oracle sample length (0 = auto)")
+    ap.add_argument("--no-fp32", action="store_true", help="skip the FP32 variant")
+    ap.add_argument("--copy-mib", type=int, default=0,
+                    help="also run a plain device copy of this many MiB (counter calibration)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on exactly one GPU (no sharding or "
+                                   "collectives); run with --gpus 1"}))
+        return 2
+
+    cfg = WORKLOADS[args.workload]()
+    r64 = measure(cfg, args, "fp64")
+    r32 = measure(W.with_(cfg, precision="fp32"), args, "fp32") if not args.no_fp32 else None
+    value, elapsed, ne_avg, ni_avg = r64["value"], r64["elapsed"], r64["ne"], r64["ni"]
+    S = int(cfg["ion_subcycle"])
 
     out = {
         "metric": "particle-steps/s at 1 GPU (plain FP64) + % HBM peak",
@@ -142,17 +163,27 @@ def main() -> int:
                    "n_cells": cfg["n_cells"], "particles_per_cell": cfg["ppc"],
                    "electrons": int(ne_avg), "ions": int(ni_avg), "dt": cfg["dt"],
                    "ion_subcycle": S, "sort_interval": cfg["sort_interval"]},
-        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                     "kernel": "k_push_e", "avg_us": avg_s * 1e6, "launches": launches,
-                     "bytes_per_launch": bytes_per_launch,
-                     "window": "eager timed window of the same length after the graph window",
-                     "ms_per_step_eager": (t3 - t2) * 1e3 / args.steps},
+        "roofline": r64["roofline"],
     }
+    if r32 is not None:
+        out["fp32"] = {"value": r32["value"], "ms_per_step": r32["elapsed"] * 1e3 / args.steps,
+                       "dtype": "f32 particles, f64 field", "roofline": r32["roofline"],
+                       "speedup_vs_fp64": r32["value"] / value}
     if not args.no_cpu:
-        steps = args.cpu_steps or max(5, int(4.0e8 / (c0["n"][0] + c0["n"][1] / S)))
+        steps = args.cpu_steps or max(5, int(4.0e8 / (ne_avg + ni_avg / S)))
         print(f"[bench] cpu baseline: oracle, {steps} steps", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(cfg, steps)
+    if args.copy_mib > 0:
+        # a plain copy kernel of known size: its FETCH_SIZE / WRITE_SIZE under
+        # rocprofv3 --pmc calibrate the counters against bytes moved
+        import torch
+        n = args.copy_mib * (1 << 20) // 4
+        src = torch.ones(n, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        out["copy_calibration_mib"] = args.copy_mib
     print(json.dumps(out), flush=True)
     return 0
 

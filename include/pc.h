@@ -25,8 +25,10 @@
  *    pc_sync / pc_get_counts wait for the stream and surface device-side
  *    errors.  After a device-side error the handle is poisoned: further
  *    pc_step calls return PC_ERR_POISONED until pc_set_state clears it.
- *  - Particle state is structure-of-arrays, FP64: x [m] in [0, L), vx, vy,
- *    vz [m/s] (vx is the leapfrog half-step velocity), id (uint32).  Node
+ *  - Particle state is exchanged as structure-of-arrays, FP64: x [m] in
+ *    [0, L), vx, vy, vz [m/s] (vx is the leapfrog half-step velocity), id
+ *    (uint32).  FP32 columns store (cell, offset in [0,1), velocities in cells
+ *    per step) internally and convert at the state entry points.  Node
  *    arrays have pc_sizes.n_nodes entries: n_cells + 1 (bounded) or n_cells
  *    (periodic).  Charges are int64 fixed point with 25 fractional bits: a
  *    macroparticle contributes exactly 2^25 units split between its two
@@ -61,6 +63,7 @@ enum { PC_BOUNDED = 0, PC_PERIODIC = 1 };
 enum { PC_WALL_OFF = 0, PC_WALL_FIXED = 1 };
 enum { PC_SHARE_OPB = 0, PC_SHARE_EQUAL = 1 };
 enum { PC_ELECTRON = 0, PC_ION = 1 };
+enum { PC_FP64 = 0, PC_FP32 = 1 };
 /* event codes written by pc_step into the optional per-id event buffers */
 enum { PC_EV_NONE = 0, PC_EV_ELASTIC = 1, PC_EV_EXCITE = 2, PC_EV_IONIZE = 3,
        PC_EV_WALL = 4, PC_EV_ABSORB = 5, PC_EV_CX = 6, PC_EV_NULL = 7 };
@@ -73,7 +76,10 @@ enum { PC_EV_NONE = 0, PC_EV_ELASTIC = 1, PC_EV_EXCITE = 2, PC_EV_IONIZE = 3,
 typedef struct pc_config {
     int32_t bc, n_cells, ppc, ion_subcycle;
     int32_t wall_mode, energy_sharing, poisson, sort_interval;
-    int32_t launch_blocks, pad0, pad1, pad2;  /* blocks of the particle kernels (0 = auto) */
+    int32_t launch_blocks;   /* blocks of the particle kernels (0 = auto) */
+    int32_t precision;       /* PC_FP64: FP64 particle state; PC_FP32: FP32 cell-relative
+                                state and push (field solve and collision arithmetic FP64) */
+    int32_t pad1, pad2;
     double L, V, p_torr, Tg, n0, Te0_eV, Ti0_K, nu_w, dt, eps_cap, g_cap, capacity;
     double M_amu, el_A, el_B, el_p, ex_U, ex_smax, iz_U, iz_smax, cx_sigma, opb_w;
     uint64_t seed;

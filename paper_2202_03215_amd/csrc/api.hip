@@ -23,6 +23,7 @@
 using pcdev::Counters;
 using pcdev::Params;
 using pcdev::Soa;
+using pcdev::Soa32;
 
 namespace {
 
@@ -55,8 +56,17 @@ pc_status hip_fail(hipError_t e, const char* where)
 
 int64_t align256(int64_t v) { return (v + 255) & ~int64_t(255); }
 
+// Integer threshold T on the 52-bit draw k with k < T  <=>  (k + 1/2) 2^-52 < p
+// (p 2^52 - 1/2 is exact in double for p < 1).
+uint64_t thr52(double p)
+{
+    if (!(p > 0.0)) return 0;
+    if (!(p < 1.0)) return uint64_t(1) << 52;
+    return uint64_t(std::ceil(p * 4503599627370496.0 - 0.5));
+}
+
 struct Derived {
-    int nc, nn, periodic;
+    int nc, nn, periodic, fp32;
     double dx, inv_dx, dti, Ng, M, c_eps, qmdt_e, qmdt_i, W, fpc, E0;
     double sig_a, sig_e0, sig_i0, mr2, sx4, si4;
     double nu_max, P_null, T_we, T_wi, P_cx;
@@ -93,8 +103,10 @@ pc_status derive(const pc_config* c, Derived* d)
         return fail(PC_ERR_INVALID_ARG, "eps_cap, g_cap, M_amu, n0, Tg must be positive");
     if (c->sort_interval < 0) return fail(PC_ERR_INVALID_ARG, "sort_interval < 0");
     if (c->launch_blocks < 0 || c->launch_blocks > 65536) return fail(PC_ERR_INVALID_ARG, "launch_blocks");
+    if (c->precision != PC_FP64 && c->precision != PC_FP32) return fail(PC_ERR_INVALID_ARG, "precision");
     d->nc = c->n_cells;
     d->periodic = c->bc == PC_PERIODIC;
+    d->fp32 = c->precision == PC_FP32;
     d->nn = d->periodic ? d->nc : d->nc + 1;
     if (d->nn > pclaunch::max_nodes()) return fail(PC_ERR_INVALID_ARG, "too many nodes for the field solve");
     d->dx = c->L / double(d->nc);
@@ -162,7 +174,7 @@ pc_status derive(const pc_config* c, Derived* d)
 }
 
 struct Layout {
-    int64_t counters, soa[2][2][5], rho[2][2], E, births, holes[2], cand, lists, bitmap, iz, sort_cnt, sort_off, total;
+    int64_t counters, soa[2][2][6], rho[2][2], E, Ef_e, Ef_i, births, holes[2], cand, cand_w, lists, bitmap, iz, sort_cnt, sort_off, total;
 };
 
 Layout layout(const Derived& d)
@@ -175,18 +187,26 @@ Layout layout(const Derived& d)
         return at;
     };
     L.counters = take(sizeof(Counters));
+    // FP64: x, vx, vy, vz (8 B) + id; FP32: cell, offset, vx, vy, vz (4 B) + id
     for (int s = 0; s < 2; ++s)
         for (int b = 0; b < 2; ++b) {
-            for (int f = 0; f < 4; ++f) L.soa[s][b][f] = take(d.cap * 8);
-            L.soa[s][b][4] = take(d.cap * 4);
+            if (d.fp32) {
+                for (int f = 0; f < 6; ++f) L.soa[s][b][f] = take(d.cap * 4);
+            } else {
+                for (int f = 0; f < 4; ++f) L.soa[s][b][f] = take(d.cap * 8);
+                L.soa[s][b][4] = take(d.cap * 4);
+            }
         }
     for (int s = 0; s < 2; ++s)
         for (int b = 0; b < 2; ++b) L.rho[s][b] = take(int64_t(d.nn) * 8);
     L.E = take(int64_t(d.nn + 1) * 8);
+    L.Ef_e = d.fp32 ? take(int64_t(d.nn + 1) * 4) : -1;
+    L.Ef_i = d.fp32 ? take(int64_t(d.nn + 1) * 4) : -1;
     L.births = take(d.max_births * int64_t(sizeof(pcdev::Birth)));
     L.holes[0] = take(d.max_holes * 4);
     L.holes[1] = take(d.max_holes * 4);
     L.cand = take(d.cap * 4);
+    L.cand_w = take(d.cap * 8);
     L.lists = take(2 * d.max_holes * 4);
     L.bitmap = take((d.max_holes / 32 + 1) * 4);
     L.iz = take(int64_t(d.nc) * 8);
@@ -203,7 +223,9 @@ struct pc_column {
     Derived d;
     Params P;
     hipStream_t st;
-    Soa buf[2][2];
+    Soa buf[2][2];       // FP64 stores
+    Soa32 buf32[2][2];   // FP32 stores
+    int fp32;
     int cur[2];
     int64_t* rho[2][2];
     int re_cur, ri_cur;
@@ -253,9 +275,10 @@ Soa soa_of(const pc_column* h, int s) { return h->buf[s][h->cur[s]]; }
 pc_status run_sort(pc_column* h)
 {
     for (int s = 0; s < 2; ++s) {
-        const Soa src = h->buf[s][h->cur[s]];
-        const Soa dst = h->buf[s][1 - h->cur[s]];
-        HIPCHK(pclaunch::sort(h->P, s, src, dst, h->grid, h->st));
+        if (h->fp32)
+            HIPCHK(pclaunch::sort(h->P, s, h->buf32[s][h->cur[s]], h->buf32[s][1 - h->cur[s]], h->grid, h->st));
+        else
+            HIPCHK(pclaunch::sort(h->P, s, h->buf[s][h->cur[s]], h->buf[s][1 - h->cur[s]], h->grid, h->st));
         h->cur[s] = 1 - h->cur[s];
     }
     return PC_OK;
@@ -300,14 +323,25 @@ pc_status pc_init_column(const pc_config* cfg, void* workspace, size_t bytes, vo
     h->d = d;
     h->st = static_cast<hipStream_t>(hip_stream);
     char* base = static_cast<char*>(workspace);
+    h->fp32 = d.fp32;
     for (int sp = 0; sp < 2; ++sp)
         for (int b = 0; b < 2; ++b) {
-            Soa& q = h->buf[sp][b];
-            q.x = reinterpret_cast<double*>(base + L.soa[sp][b][0]);
-            q.vx = reinterpret_cast<double*>(base + L.soa[sp][b][1]);
-            q.vy = reinterpret_cast<double*>(base + L.soa[sp][b][2]);
-            q.vz = reinterpret_cast<double*>(base + L.soa[sp][b][3]);
-            q.id = reinterpret_cast<uint32_t*>(base + L.soa[sp][b][4]);
+            if (d.fp32) {
+                Soa32& q = h->buf32[sp][b];
+                q.cell = reinterpret_cast<int32_t*>(base + L.soa[sp][b][0]);
+                q.off = reinterpret_cast<float*>(base + L.soa[sp][b][1]);
+                q.vx = reinterpret_cast<float*>(base + L.soa[sp][b][2]);
+                q.vy = reinterpret_cast<float*>(base + L.soa[sp][b][3]);
+                q.vz = reinterpret_cast<float*>(base + L.soa[sp][b][4]);
+                q.id = reinterpret_cast<uint32_t*>(base + L.soa[sp][b][5]);
+            } else {
+                Soa& q = h->buf[sp][b];
+                q.x = reinterpret_cast<double*>(base + L.soa[sp][b][0]);
+                q.vx = reinterpret_cast<double*>(base + L.soa[sp][b][1]);
+                q.vy = reinterpret_cast<double*>(base + L.soa[sp][b][2]);
+                q.vz = reinterpret_cast<double*>(base + L.soa[sp][b][3]);
+                q.id = reinterpret_cast<uint32_t*>(base + L.soa[sp][b][4]);
+            }
             h->rho[sp][b] = reinterpret_cast<int64_t*>(base + L.rho[sp][b]);
         }
     Params& P = h->P;
@@ -348,6 +382,16 @@ pc_status pc_init_column(const pc_config* cfg, void* workspace, size_t bytes, vo
     P.V = cfg->V;
     P.key0 = uint32_t(cfg->seed);
     P.key1 = uint32_t(cfg->seed >> 32);
+    P.kn_e = thr52(d.P_null);
+    P.kw_e = thr52(d.T_we);
+    P.kw_i = thr52(d.T_wi);
+    P.kcx = thr52(d.P_cx);
+    P.u2v_e = d.dx / cfg->dt;
+    P.u2v_i = d.dx / d.dti;
+    P.efs_e = (-kQe * cfg->dt * cfg->dt) / (kMe * d.dx);
+    P.efs_i = (kQe * d.dti * d.dti) / (d.M * d.dx);
+    P.Ef_e = d.fp32 ? reinterpret_cast<float*>(base + L.Ef_e) : nullptr;
+    P.Ef_i = d.fp32 ? reinterpret_cast<float*>(base + L.Ef_i) : nullptr;
     P.cap = d.cap;
     P.max_births = d.max_births;
     P.max_holes = d.max_holes;
@@ -356,6 +400,7 @@ pc_status pc_init_column(const pc_config* cfg, void* workspace, size_t bytes, vo
     P.holes[0] = reinterpret_cast<uint32_t*>(base + L.holes[0]);
     P.holes[1] = reinterpret_cast<uint32_t*>(base + L.holes[1]);
     P.cand = reinterpret_cast<uint32_t*>(base + L.cand);
+    P.cand_w = reinterpret_cast<uint2*>(base + L.cand_w);
     P.lists = reinterpret_cast<uint32_t*>(base + L.lists);
     P.bitmap = reinterpret_cast<uint32_t*>(base + L.bitmap);
     P.iz = reinterpret_cast<int64_t*>(base + L.iz);
@@ -383,13 +428,30 @@ pc_status pc_init_column(const pc_config* cfg, void* workspace, size_t bytes, vo
         for (int b = 0; b < 2 && e == hipSuccess; ++b) e = pclaunch::fill_i64(h->rho[sp][b], d.nn, 0, h->st);
     if (e == hipSuccess) e = pclaunch::fill_i64(P.iz, d.nc, 0, h->st);
     if (e == hipSuccess) e = pclaunch::fill_i64(reinterpret_cast<int64_t*>(P.sort_cnt), (d.nc + 1) / 2, 0, h->st);
-    if (e == hipSuccess) e = pclaunch::load(P, 0, h->buf[0][0], d.n0, d.sig_e0, h->st);
-    if (e == hipSuccess) e = pclaunch::load(P, 1, h->buf[1][0], d.n0, d.sig_i0, h->st);
-    if (e == hipSuccess) e = pclaunch::deposit(P, h->buf[0][0].x, d.n0, h->rho[0][0], h->st);
-    if (e == hipSuccess) e = pclaunch::deposit(P, h->buf[1][0].x, d.n0, h->rho[1][0], h->st);
+    if (d.fp32) {
+        // FP32 columns: the loader draws in FP64 and converts each particle
+        if (e == hipSuccess) e = pclaunch::load(P, 0, h->buf32[0][0], d.n0, d.sig_e0, h->st);
+        if (e == hipSuccess) e = pclaunch::load(P, 1, h->buf32[1][0], d.n0, d.sig_i0, h->st);
+    } else {
+        if (e == hipSuccess) e = pclaunch::load(P, 0, h->buf[0][0], d.n0, d.sig_e0, h->st);
+        if (e == hipSuccess) e = pclaunch::load(P, 1, h->buf[1][0], d.n0, d.sig_i0, h->st);
+        if (e == hipSuccess) e = pclaunch::deposit(P, h->buf[0][0].x, d.n0, h->rho[0][0], h->st);
+        if (e == hipSuccess) e = pclaunch::deposit(P, h->buf[1][0].x, d.n0, h->rho[1][0], h->st);
+    }
+    if (e != hipSuccess) return cleanup(hip_fail(e, "pc_init_column launch"));
+    if (d.fp32) {
+        e = pclaunch::deposit(P, h->buf32[0][0], d.n0, h->rho[0][0], h->st);
+        if (e == hipSuccess) e = pclaunch::deposit(P, h->buf32[1][0], d.n0, h->rho[1][0], h->st);
+    }
     if (e == hipSuccess) e = pclaunch::field(P, h->rho[0][0], h->rho[1][0], P.E, nullptr, 1, h->st);
-    if (e == hipSuccess) e = pclaunch::halfstep(P, h->buf[0][0], d.n0, 0.5 * d.qmdt_e, h->st);
-    if (e == hipSuccess) e = pclaunch::halfstep(P, h->buf[1][0], d.n0, 0.5 * d.qmdt_i, h->st);
+    if (e == hipSuccess) e = pclaunch::scale_field(P, h->st);
+    if (d.fp32) {
+        if (e == hipSuccess) e = pclaunch::halfstep(P, h->buf32[0][0], 0, d.n0, h->st);
+        if (e == hipSuccess) e = pclaunch::halfstep(P, h->buf32[1][0], 1, d.n0, h->st);
+    } else {
+        if (e == hipSuccess) e = pclaunch::halfstep(P, h->buf[0][0], d.n0, 0.5 * d.qmdt_e, h->st);
+        if (e == hipSuccess) e = pclaunch::halfstep(P, h->buf[1][0], d.n0, 0.5 * d.qmdt_i, h->st);
+    }
     if (e != hipSuccess) return cleanup(hip_fail(e, "pc_init_column launch"));
     if (cfg->sort_interval > 0 && (s = run_sort(h)) != PC_OK) return cleanup(s);
     if ((s = read_counters(h)) != PC_OK) return cleanup(s);
@@ -410,12 +472,20 @@ static pc_status enqueue_step(pc_column* h, bool time_it, int64_t slot)
     int64_t* re_old = h->rho[0][h->re_cur];
     int64_t* ri_use = ion ? h->rho[1][1 - h->ri_cur] : h->rho[1][h->ri_cur];
     int64_t* ri_old = ion ? h->rho[1][h->ri_cur] : nullptr;
-    const Soa se = soa_of(h, 0), si = soa_of(h, 1);
     if (time_it) HIPCHK(hipEventRecord(h->tev[2 * slot], h->st));
-    HIPCHK(pclaunch::advance(h->P, 0, se, re_new, h->ev[0], h->evlen[0], h->grid, h->st));
-    if (time_it) HIPCHK(hipEventRecord(h->tev[2 * slot + 1], h->st));
-    if (ion) HIPCHK(pclaunch::advance(h->P, 1, si, ri_use, h->ev[1], h->evlen[1], h->grid, h->st));
-    HIPCHK(pclaunch::finish(h->P, se, si, re_new, ri_use, re_old, ri_old, h->st));
+    if (h->fp32) {
+        const Soa32 se = h->buf32[0][h->cur[0]], si = h->buf32[1][h->cur[1]];
+        HIPCHK(pclaunch::advance(h->P, 0, se, re_new, h->ev[0], h->evlen[0], h->grid, h->st));
+        if (time_it) HIPCHK(hipEventRecord(h->tev[2 * slot + 1], h->st));
+        if (ion) HIPCHK(pclaunch::advance(h->P, 1, si, ri_use, h->ev[1], h->evlen[1], h->grid, h->st));
+        HIPCHK(pclaunch::finish(h->P, se, si, re_new, ri_use, re_old, ri_old, h->st));
+    } else {
+        const Soa se = soa_of(h, 0), si = soa_of(h, 1);
+        HIPCHK(pclaunch::advance(h->P, 0, se, re_new, h->ev[0], h->evlen[0], h->grid, h->st));
+        if (time_it) HIPCHK(hipEventRecord(h->tev[2 * slot + 1], h->st));
+        if (ion) HIPCHK(pclaunch::advance(h->P, 1, si, ri_use, h->ev[1], h->evlen[1], h->grid, h->st));
+        HIPCHK(pclaunch::finish(h->P, se, si, re_new, ri_use, re_old, ri_old, h->st));
+    }
     h->re_cur = 1 - h->re_cur;
     if (ion) h->ri_cur = 1 - h->ri_cur;
     h->step += 1;
@@ -545,7 +615,11 @@ pc_status pc_moments(pc_handle h, int32_t cells_per_group, int32_t reset_iz, int
     if (!h || !out || cells_per_group < 1) return fail(PC_ERR_INVALID_ARG, "bad moments arguments");
     const int64_t ng = (h->d.nc + cells_per_group - 1) / cells_per_group;
     const int64_t len = 7 * int64_t(h->d.nc) + ng * 240;
-    HIPCHK(pclaunch::moments(h->P, soa_of(h, 0), soa_of(h, 1), cells_per_group, reset_iz, out, len, h->st));
+    if (h->fp32)
+        HIPCHK(pclaunch::moments(h->P, h->buf32[0][h->cur[0]], h->buf32[1][h->cur[1]], cells_per_group, reset_iz,
+                                 out, len, h->st));
+    else
+        HIPCHK(pclaunch::moments(h->P, soa_of(h, 0), soa_of(h, 1), cells_per_group, reset_iz, out, len, h->st));
     return PC_OK;
 }
 
@@ -571,8 +645,13 @@ pc_status pc_get_state(pc_handle h, int32_t species, double* x, double* vx, doub
     pc_status s = read_counters(h);
     if (s != PC_OK) return s;
     const int64_t n = std::min<int64_t>(cap, h->host_cnt.n[species]);
-    const Soa q = soa_of(h, species);
     if (n == 0) return PC_OK;
+    if (h->fp32) {
+        const Soa dst{x, vx, vy, vz, id};
+        HIPCHK(pclaunch::to64(h->P, h->buf32[species][h->cur[species]], dst, n, species, h->st));
+        return PC_OK;
+    }
+    const Soa q = soa_of(h, species);
     if (x) HIPCHK(hipMemcpyAsync(x, q.x, n * 8, hipMemcpyDeviceToDevice, h->st));
     if (vx) HIPCHK(hipMemcpyAsync(vx, q.vx, n * 8, hipMemcpyDeviceToDevice, h->st));
     if (vy) HIPCHK(hipMemcpyAsync(vy, q.vy, n * 8, hipMemcpyDeviceToDevice, h->st));
@@ -590,7 +669,7 @@ pc_status pc_set_state(pc_handle h, int32_t species, int64_t n, const double* x,
     pc_status s = read_counters(h);
     if (s != PC_OK) return s;
     const Soa q = soa_of(h, species);
-    if (n > 0) {
+    if (!h->fp32 && n > 0) {
         HIPCHK(hipMemcpyAsync(q.x, x, n * 8, hipMemcpyDeviceToDevice, h->st));
         HIPCHK(hipMemcpyAsync(q.vx, vx, n * 8, hipMemcpyDeviceToDevice, h->st));
         HIPCHK(hipMemcpyAsync(q.vy, vy, n * 8, hipMemcpyDeviceToDevice, h->st));
@@ -603,10 +682,17 @@ pc_status pc_set_state(pc_handle h, int32_t species, int64_t n, const double* x,
     h->host_cnt.nh[0] = h->host_cnt.nh[1] = 0;
     if ((s = write_counters(h)) != PC_OK) return s;
     // positions must lie in [0, L): checked by a deposit into scratch charge
-    if (n > 0) {
+    // (the FP32 conversion checks them itself)
+    if (n > 0 && h->fp32) {
+        const Soa src{const_cast<double*>(x), const_cast<double*>(vx), const_cast<double*>(vy),
+                      const_cast<double*>(vz), const_cast<uint32_t*>(id)};
+        HIPCHK(pclaunch::from64(h->P, src, h->buf32[species][h->cur[species]], n, species, h->st));
+    } else if (n > 0) {
         int64_t* scratch = h->rho[0][1 - h->re_cur];   // the next electron charge buffer: zero and unused
         HIPCHK(pclaunch::deposit(h->P, q.x, n, scratch, h->st));
         HIPCHK(pclaunch::fill_i64(scratch, h->d.nn, 0, h->st));
+    }
+    if (n > 0) {
         if ((s = read_counters(h)) != PC_OK) return s;
         if (h->host_cnt.err) {
             h->poisoned = 1;
@@ -647,6 +733,7 @@ pc_status pc_set_field(pc_handle h, const double* E)
     if (!h || !E) return fail(PC_ERR_INVALID_ARG, "null argument");
     HIPCHK(hipMemcpyAsync(h->P.E, E, int64_t(h->d.nn) * 8, hipMemcpyDeviceToDevice, h->st));
     if (h->d.periodic) HIPCHK(hipMemcpyAsync(h->P.E + h->d.nc, E, 8, hipMemcpyDeviceToDevice, h->st));
+    HIPCHK(pclaunch::scale_field(h->P, h->st));
     return PC_OK;
 }
 

@@ -54,11 +54,22 @@ struct Birth {           // one ionization event (64 bytes)
     double pad;
 };
 
-struct Soa {             // one structure-of-arrays particle buffer
+struct Soa {             // one structure-of-arrays particle buffer (FP64)
     double* x;
     double* vx;
     double* vy;
     double* vz;
+    uint32_t* id;
+};
+
+// FP32 particle buffer: cell-relative position (cell index, offset in [0,1))
+// and velocities in cells per step of the species (electron: dt, ion: S dt)
+struct Soa32 {
+    int32_t* cell;
+    float* off;
+    float* vx;
+    float* vy;
+    float* vz;
     uint32_t* id;
 };
 
@@ -75,12 +86,21 @@ struct Params {
     // field
     double fpc, E0, V;
     uint32_t key0, key1;
+    // integer forms of the per-step thresholds on the 52-bit draw k = r >> 12
+    // (k < T is the same decision as (k + 1/2) 2^-52 < P for T = ceil(P 2^52 - 1/2))
+    uint64_t kn_e, kw_e, kw_i, kcx;
+    // FP32 path: velocity scales (m/s per cell/step) and field scales
+    double u2v_e, u2v_i;            // dx/dt, dx/dt_i
+    double efs_e, efs_i;            // q dt^2/(m dx), q dt_i^2/(M dx)
+    float* Ef_e;                    // E scaled to cells/step^2, n_nodes + 1 (ghost)
+    float* Ef_i;
     int64_t cap, max_births, max_holes;
     Counters* cnt;
     Birth* births;
     uint32_t* holes[2];
     uint32_t* cand;      // electron collision candidates (slot indices): each block of
                          // the push kernel lists its own from the start of its chunk
+    uint2* cand_w;       // their Philox block-0 words 2, 3 (the process draw u1)
     uint32_t* lists;     // compaction scratch: 2 * max_holes entries
     uint32_t* bitmap;    // compaction scratch: max_holes bits
     int64_t* iz;         // ionizations per cell

@@ -145,14 +145,134 @@ __device__ __forceinline__ bool apply_boundary(const Params& P, double& x, uint8
     return false;
 }
 
+// --------------------------------------------------- particle-store access
+// FP64 stores keep x [m] and v [m/s]; FP32 stores keep (cell, offset) and
+// velocities in cells per step.  Collision arithmetic is FP64 for both.
+__device__ __forceinline__ void load_v(const Params&, const Soa& s, uint32_t i, int, double& vx, double& vy,
+                                       double& vz)
+{
+    vx = s.vx[i];
+    vy = s.vy[i];
+    vz = s.vz[i];
+}
+__device__ __forceinline__ void load_v(const Params& P, const Soa32& s, uint32_t i, int sp, double& vx,
+                                       double& vy, double& vz)
+{
+    const double k = sp == kElectron ? P.u2v_e : P.u2v_i;
+    vx = double(s.vx[i]) * k;
+    vy = double(s.vy[i]) * k;
+    vz = double(s.vz[i]) * k;
+}
+__device__ __forceinline__ void store_v(const Params&, const Soa& s, uint32_t i, int, double vx, double vy,
+                                        double vz)
+{
+    s.vx[i] = vx;
+    s.vy[i] = vy;
+    s.vz[i] = vz;
+}
+__device__ __forceinline__ void store_v(const Params& P, const Soa32& s, uint32_t i, int sp, double vx,
+                                        double vy, double vz)
+{
+    const double k = sp == kElectron ? P.u2v_e : P.u2v_i;
+    s.vx[i] = float(vx / k);
+    s.vy[i] = float(vy / k);
+    s.vz[i] = float(vz / k);
+}
+// position key of a particle: x [m] (FP64) or cell + offset (FP32, exact in FP64)
+__device__ __forceinline__ double pos_key(const Params&, const Soa& s, uint32_t i) { return s.x[i]; }
+__device__ __forceinline__ double pos_key(const Params&, const Soa32& s, uint32_t i)
+{
+    return double(s.cell[i]) + double(s.off[i]);
+}
+// cell and 25-bit weight of a position key
+__device__ __forceinline__ int key_cell(const Params& P, const Soa&, double xk, int64_t& a)
+{
+    double f;
+    const int j = cell_frac(P, xk, f);
+    a = frac_units(f);
+    return j;
+}
+__device__ __forceinline__ int key_cell(const Params& P, const Soa32&, double xk, int64_t& a)
+{
+    int c = int(xk);
+    if (c > P.nc - 1) c = P.nc - 1;
+    if (c < 0) c = 0;
+    a = frac_units(float(xk - double(c)));
+    return c;
+}
+__device__ __forceinline__ void move_particle(const Soa& sp, uint32_t dst, uint32_t src)
+{
+    sp.x[dst] = sp.x[src];
+    sp.vx[dst] = sp.vx[src];
+    sp.vy[dst] = sp.vy[src];
+    sp.vz[dst] = sp.vz[src];
+    sp.id[dst] = sp.id[src];
+}
+__device__ __forceinline__ void move_particle(const Soa32& sp, uint32_t dst, uint32_t src)
+{
+    sp.cell[dst] = sp.cell[src];
+    sp.off[dst] = sp.off[src];
+    sp.vx[dst] = sp.vx[src];
+    sp.vy[dst] = sp.vy[src];
+    sp.vz[dst] = sp.vz[src];
+    sp.id[dst] = sp.id[src];
+}
+// write a new particle at slot p from a position key and a velocity [m/s]
+__device__ __forceinline__ void put_particle(const Params& P, const Soa& s, int64_t p, int, double xk,
+                                             const double v[3], uint32_t id)
+{
+    s.x[p] = xk;
+    s.vx[p] = v[0];
+    s.vy[p] = v[1];
+    s.vz[p] = v[2];
+    s.id[p] = id;
+}
+__device__ __forceinline__ void put_particle(const Params& P, const Soa32& s, int64_t p, int sp, double xk,
+                                             const double v[3], uint32_t id)
+{
+    int c = int(xk);
+    if (c > P.nc - 1) c = P.nc - 1;
+    s.cell[p] = c;
+    s.off[p] = float(xk - double(c));
+    store_v(P, s, uint32_t(p), sp, v[0], v[1], v[2]);
+    s.id[p] = id;
+}
+
+// cell index of particle i
+__device__ __forceinline__ int cell_at(const Params& P, const Soa& s, int64_t i)
+{
+    double f;
+    return cell_frac(P, s.x[i], f);
+}
+__device__ __forceinline__ int cell_at(const Params&, const Soa32& s, int64_t i) { return s.cell[i]; }
+__device__ __forceinline__ void copy_particle(const Soa& d, int64_t p, const Soa& s, int64_t i)
+{
+    d.x[p] = s.x[i];
+    d.vx[p] = s.vx[i];
+    d.vy[p] = s.vy[i];
+    d.vz[p] = s.vz[i];
+    d.id[p] = s.id[i];
+}
+__device__ __forceinline__ void copy_particle(const Soa32& d, int64_t p, const Soa32& s, int64_t i)
+{
+    d.cell[p] = s.cell[i];
+    d.off[p] = s.off[i];
+    d.vx[p] = s.vx[i];
+    d.vy[p] = s.vy[i];
+    d.vz[p] = s.vz[i];
+    d.id[p] = s.id[i];
+}
+
+__device__ __forceinline__ uint64_t draw52(uint32_t lo, uint32_t hi) { return ((uint64_t(hi) << 32) | lo) >> 12; }
+
 // -------------------------------------------------------- electron collide
 // One collision candidate: choose the process with u1 nu_max against the
 // cumulative collision frequencies (elastic, excitation, ionization, else
 // null), then scatter.  Ionizations (rare) are listed with the parent's slot,
 // position and energy; their kinematics run in the finish kernel.
-template <bool EV>
-__device__ __forceinline__ void collide_one(const Params& P, const Soa& sp, uint8_t* __restrict__ ev,
-                                            int64_t evlen, uint32_t step, bool act, uint32_t i)
+template <bool EV, class St>
+__device__ __forceinline__ void collide_one(const Params& P, const St& sp, uint8_t* __restrict__ ev,
+                                            int64_t evlen, uint32_t step, bool act, uint32_t i, uint2 wcd)
 {
     const uint32_t stream = kStreamElectronStep;
     bool born = false;
@@ -160,10 +280,10 @@ __device__ __forceinline__ void collide_one(const Params& P, const Soa& sp, uint
     int jn = 0;
     double x = 0.0, epsb = 0.0;
     if (act) {
-        double vx = sp.vx[i], vy = sp.vy[i], vz = sp.vz[i];
+        double vx, vy, vz;
+        load_v(P, sp, i, kElectron, vx, vy, vz);
         id = sp.id[i];
-        const U4 w = philox10(id, step, 0u, stream, P.key0, P.key1);
-        const double u1 = unif52(w.c, w.d);
+        const double u1 = unif52(wcd.x, wcd.y);   // words 2, 3 of the step's block 0
         const double v2 = (vx * vx + vy * vy) + vz * vz;
         const double eps = P.c_eps * v2;
         const double v = sqrt(v2);
@@ -191,15 +311,13 @@ __device__ __forceinline__ void collide_one(const Params& P, const Soa& sp, uint
                     code = kEvExcite;
                     vn = sqrt((eps - P.ex_U) / P.c_eps);
                 }
-                sp.vx[i] = vn * nx;
-                sp.vy[i] = vn * ny;
-                sp.vz[i] = vn * nz;
+                store_v(P, sp, i, kElectron, vn * nx, vn * ny, vn * nz);
             } else {
                 code = kEvIonize;
-                x = sp.x[i];
+                x = pos_key(P, sp, i);
                 epsb = eps;
-                double f;
-                jn = cell_frac(P, x, f);
+                int64_t a_unused;
+                jn = key_cell(P, sp, x, a_unused);
                 born = true;
             }
         }
@@ -248,17 +366,33 @@ __global__ __launch_bounds__(kAdvBlock) void k_push_e(Params P, Soa sp, int64_t*
     __syncthreads();
     const double* __restrict__ E = P.E;
     uint32_t* __restrict__ cl = P.cand + beg;   // this block's candidate segment
-
+    uint2* __restrict__ cw = P.cand_w + beg;
+    // software pipeline: the next tile's loads are issued before this tile's work
+    double px = 0.0, pvx = 0.0;
+    uint32_t pid = 0;
+    {
+        const int64_t i = beg + threadIdx.x;
+        if (i < end) {
+            px = sp.x[i];
+            pvx = sp.vx[i];
+            pid = sp.id[i];
+        }
+    }
     for (int64_t i0 = beg; i0 < end; i0 += kAdvBlock) {
         const int64_t i = i0 + threadIdx.x;
         const bool act = i < end;
         bool alive = false, cand = false;
         int jn = 0;
         int64_t an = 0;
+        uint2 wcd = make_uint2(0u, 0u);
+        double x = px, vx = pvx;
+        const uint32_t id = pid;
+        if (i + kAdvBlock < end) {
+            px = sp.x[i + kAdvBlock];
+            pvx = sp.vx[i + kAdvBlock];
+            pid = sp.id[i + kAdvBlock];
+        }
         if (act) {
-            double x = sp.x[i];
-            double vx = sp.vx[i];
-            const uint32_t id = sp.id[i];
             double f;
             const int j = cell_frac(P, x, f);
             const double Ex = E[j] + f * (E[j + 1] - E[j]);
@@ -268,13 +402,14 @@ __global__ __launch_bounds__(kAdvBlock) void k_push_e(Params P, Soa sp, int64_t*
             alive = apply_boundary(P, x, code);
             if (alive) {
                 const U4 w = philox10(id, step, 0u, kStreamElectronStep, P.key0, P.key1);
-                const double u0 = unif52(w.a, w.b);
-                if (u0 >= P.T_we) {
+                const uint64_t k0 = draw52(w.a, w.b);
+                if (k0 >= P.kw_e) {
                     alive = false;
                     code = kEvWall;
                 } else {
-                    cand = u0 < P.P_null;
+                    cand = k0 < P.kn_e;
                 }
+                wcd = make_uint2(w.c, w.d);
             }
             if (alive) {
                 sp.x[i] = x;
@@ -297,7 +432,11 @@ __global__ __launch_bounds__(kAdvBlock) void k_push_e(Params P, Soa sp, int64_t*
                 int base = 0;
                 if (lane_id() == leader) base = atomicAdd(&ncand, __popcll((unsigned long long)m));
                 base = __shfl(base, leader);
-                if (cand) cl[base + int(lanes_below(m))] = uint32_t(i);
+                if (cand) {
+                    const int q = base + int(lanes_below(m));
+                    cl[q] = uint32_t(i);
+                    cw[q] = wcd;
+                }
             }
         }
         deposit_wave(P, win, wbase, rho, alive, jn, an);
@@ -314,7 +453,8 @@ __global__ __launch_bounds__(kAdvBlock) void k_push_e(Params P, Soa sp, int64_t*
     const int nc = ncand;
     for (int k0 = 0; k0 < nc; k0 += kAdvBlock) {
         const int k = k0 + int(threadIdx.x);
-        collide_one<EV>(P, sp, ev, evlen, step, k < nc, k < nc ? cl[k] : 0u);
+        collide_one<EV>(P, sp, ev, evlen, step, k < nc, k < nc ? cl[k] : 0u,
+                        k < nc ? cw[k] : make_uint2(0u, 0u));
     }
 }
 
@@ -358,12 +498,12 @@ __global__ __launch_bounds__(kAdvBlock) void k_advance_i(Params P, Soa sp, int64
             alive = apply_boundary(P, x, code);
             if (alive) {
                 const U4 w = philox10(id, step, 0u, kStreamIonStep, P.key0, P.key1);
-                const double u0 = unif52(w.a, w.b);
+                const uint64_t k0 = draw52(w.a, w.b);
                 const double u1 = unif52(w.c, w.d);
-                if (u0 >= P.T_wi) {
+                if (k0 >= P.kw_i) {
                     alive = false;
                     code = kEvWall;
-                } else if (u0 < P.P_cx) {
+                } else if (k0 < P.kcx) {
                     double vy = sp.vy[i], vz = sp.vz[i];
                     WordStream ws(id, step, kStreamIonStep, P.key0, P.key1);
                     double g0, g1, g2;
@@ -407,6 +547,328 @@ __global__ __launch_bounds__(kAdvBlock) void k_advance_i(Params P, Soa sp, int64
             const int node = wbase + k;
             if (node >= 0 && node < P.nn) atomicAdd((unsigned long long*)&rho[node], v);
         }
+    }
+}
+
+// ================================================================ FP32 path
+// Cell-relative FP32 state: position = cell + offset (offset in [0,1)), so
+// resolution does not degrade along the column; velocities in cells per step
+// of the species.  Gather and push run in FP32 against the field scaled to
+// cells/step^2 (Ef = q dt^2 E / (m dx)); collision candidates convert to FP64
+// and share the FP64 collision code; the field solve stays FP64.
+
+__device__ __forceinline__ int64_t frac_units32(float off)
+{
+    return int64_t(uint32_t(off * 33554432.0f));   // off * 2^25 is exact in FP32
+}
+
+// one FP32 leapfrog step; returns false if the particle left a bounded column
+__device__ __forceinline__ bool push32(const Params& P, const float* __restrict__ Ef, int& c, float& off,
+                                       float& u, uint8_t& code)
+{
+    const float e0 = Ef[c], e1 = Ef[c + 1];
+    u = u + (e0 + off * (e1 - e0));
+    off = off + u;
+    const float fl = floorf(off);
+    c += int(fl);
+    off = off - fl;
+    if (off >= 1.0f) {
+        off = 0.0f;
+        c += 1;
+    }
+    if (!(off >= 0.0f && off < 1.0f)) {   // NaN
+        set_err(P, kErrRange);
+        off = 0.0f;
+    }
+    if (P.periodic) {
+        if (c >= P.nc) c -= P.nc;
+        else if (c < 0) c += P.nc;
+        if (c < 0 || c >= P.nc) {
+            set_err(P, kErrRange);
+            c = 0;
+            off = 0.0f;
+        }
+        return true;
+    }
+    if (c >= 0 && c < P.nc) return true;
+    code = kEvAbsorb;
+    return false;
+}
+
+template <bool EV>
+__global__ __launch_bounds__(kAdvBlock) void k_push_e32(Params P, Soa32 sp, int64_t* __restrict__ rho,
+                                                       uint8_t* __restrict__ ev, int64_t evlen)
+{
+    __shared__ unsigned long long win[kWindow];
+    __shared__ int ncand;
+    const int64_t n = P.cnt->n[kElectron];
+    const uint32_t step = uint32_t(P.cnt->step);
+    int64_t beg, end;
+    block_chunk(n, beg, end);
+    if (beg >= end) return;
+    for (int k = threadIdx.x; k < kWindow; k += kAdvBlock) win[k] = 0ull;
+    if (threadIdx.x == 0) ncand = 0;
+    const int wbase = sp.cell[beg] - kHalo;
+    __syncthreads();
+    uint32_t* __restrict__ cl = P.cand + beg;
+    uint2* __restrict__ cw = P.cand_w + beg;
+    int pc = 0;
+    float poff = 0.0f, pu = 0.0f;
+    uint32_t pid = 0;
+    {
+        const int64_t i = beg + threadIdx.x;
+        if (i < end) {
+            pc = sp.cell[i];
+            poff = sp.off[i];
+            pu = sp.vx[i];
+            pid = sp.id[i];
+        }
+    }
+    for (int64_t i0 = beg; i0 < end; i0 += kAdvBlock) {
+        const int64_t i = i0 + threadIdx.x;
+        const bool act = i < end;
+        bool alive = false, cand = false;
+        int jn = 0;
+        int64_t an = 0;
+        uint2 wcd = make_uint2(0u, 0u);
+        int c = pc;
+        float off = poff, u = pu;
+        const uint32_t id = pid;
+        if (i + kAdvBlock < end) {
+            pc = sp.cell[i + kAdvBlock];
+            poff = sp.off[i + kAdvBlock];
+            pu = sp.vx[i + kAdvBlock];
+            pid = sp.id[i + kAdvBlock];
+        }
+        if (act) {
+            uint8_t code = kEvNone;
+            alive = push32(P, P.Ef_e, c, off, u, code);
+            if (alive) {
+                const U4 w = philox10(id, step, 0u, kStreamElectronStep, P.key0, P.key1);
+                const uint64_t k0 = draw52(w.a, w.b);
+                if (k0 >= P.kw_e) {
+                    alive = false;
+                    code = kEvWall;
+                } else {
+                    cand = k0 < P.kn_e;
+                }
+                wcd = make_uint2(w.c, w.d);
+            }
+            if (alive) {
+                sp.cell[i] = c;
+                sp.off[i] = off;
+                sp.vx[i] = u;
+                jn = c;
+                an = frac_units32(off);
+            }
+            if (EV && !cand && int64_t(id) < evlen) ev[id] = code;
+        }
+        const int64_t hp = wave_append(act && !alive, &P.cnt->nh[kElectron]);
+        if (hp >= 0) {
+            if (hp < P.max_holes) P.holes[kElectron][hp] = uint32_t(i);
+            else set_err(P, kErrLosses);
+        }
+        {
+            const uint64_t m = __ballot(cand);
+            if (m != 0) {
+                const int leader = __ffsll((unsigned long long)m) - 1;
+                int base = 0;
+                if (lane_id() == leader) base = atomicAdd(&ncand, __popcll((unsigned long long)m));
+                base = __shfl(base, leader);
+                if (cand) {
+                    const int q = base + int(lanes_below(m));
+                    cl[q] = uint32_t(i);
+                    cw[q] = wcd;
+                }
+            }
+        }
+        deposit_wave(P, win, wbase, rho, alive, jn, an);
+    }
+    __syncthreads();
+    for (int k = threadIdx.x; k < kWindow; k += kAdvBlock) {
+        const unsigned long long v = win[k];
+        if (v != 0ull) {
+            const int node = wbase + k;
+            if (node >= 0 && node < P.nn) atomicAdd((unsigned long long*)&rho[node], v);
+        }
+    }
+    const int nc = ncand;
+    for (int k0 = 0; k0 < nc; k0 += kAdvBlock) {
+        const int k = k0 + int(threadIdx.x);
+        collide_one<EV>(P, sp, ev, evlen, step, k < nc, k < nc ? cl[k] : 0u,
+                        k < nc ? cw[k] : make_uint2(0u, 0u));
+    }
+}
+
+template <bool EV>
+__global__ __launch_bounds__(kAdvBlock) void k_advance_i32(Params P, Soa32 sp, int64_t* __restrict__ rho,
+                                                          uint8_t* __restrict__ ev, int64_t evlen)
+{
+    __shared__ unsigned long long win[kWindow];
+    const int64_t n = P.cnt->n[kIon];
+    const uint32_t step = uint32_t(P.cnt->step);
+    int64_t beg, end;
+    block_chunk(n, beg, end);
+    if (beg >= end) return;
+    for (int k = threadIdx.x; k < kWindow; k += kAdvBlock) win[k] = 0ull;
+    const int wbase = sp.cell[beg] - kHalo;
+    __syncthreads();
+    for (int64_t i0 = beg; i0 < end; i0 += kAdvBlock) {
+        const int64_t i = i0 + threadIdx.x;
+        const bool act = i < end;
+        bool alive = false;
+        int jn = 0;
+        int64_t an = 0;
+        if (act) {
+            int c = sp.cell[i];
+            float off = sp.off[i];
+            float u = sp.vx[i];
+            const uint32_t id = sp.id[i];
+            uint8_t code = kEvNone;
+            alive = push32(P, P.Ef_i, c, off, u, code);
+            if (alive) {
+                const U4 w = philox10(id, step, 0u, kStreamIonStep, P.key0, P.key1);
+                const uint64_t k0 = draw52(w.a, w.b);
+                if (k0 >= P.kw_i) {
+                    alive = false;
+                    code = kEvWall;
+                } else if (k0 < P.kcx) {
+                    const double u1 = unif52(w.c, w.d);
+                    const double vx = double(u) * P.u2v_i;
+                    const double vy = double(sp.vy[i]) * P.u2v_i;
+                    const double vz = double(sp.vz[i]) * P.u2v_i;
+                    WordStream ws(id, step, kStreamIonStep, P.key0, P.key1);
+                    double g0, g1, g2;
+                    normal3(ws, g0, g1, g2);
+                    const double ax = P.sig_a * g0, ay = P.sig_a * g1, az = P.sig_a * g2;
+                    const double dx = vx - ax, dy = vy - ay, dz = vz - az;
+                    const double g = sqrt((dx * dx + dy * dy) + dz * dz);
+                    if (g > P.g_cap) set_err(P, kErrGCap);
+                    if (u1 * P.g_cap < g) {
+                        code = kEvCX;
+                        u = float(ax / P.u2v_i);
+                        sp.vy[i] = float(ay / P.u2v_i);
+                        sp.vz[i] = float(az / P.u2v_i);
+                    } else {
+                        code = kEvNull;
+                    }
+                }
+            }
+            if (alive) {
+                sp.cell[i] = c;
+                sp.off[i] = off;
+                sp.vx[i] = u;
+                jn = c;
+                an = frac_units32(off);
+            }
+            if (EV && int64_t(id) < evlen) ev[id] = code;
+        }
+        const int64_t hp = wave_append(act && !alive, &P.cnt->nh[kIon]);
+        if (hp >= 0) {
+            if (hp < P.max_holes) P.holes[kIon][hp] = uint32_t(i);
+            else set_err(P, kErrLosses);
+        }
+        deposit_wave(P, win, wbase, rho, alive, jn, an);
+    }
+    __syncthreads();
+    for (int k = threadIdx.x; k < kWindow; k += kAdvBlock) {
+        const unsigned long long v = win[k];
+        if (v != 0ull) {
+            const int node = wbase + k;
+            if (node >= 0 && node < P.nn) atomicAdd((unsigned long long*)&rho[node], v);
+        }
+    }
+}
+
+// FP64 position/velocity -> FP32 cell-relative state
+__device__ __forceinline__ void to32(const Params& P, double x, double vx, double vy, double vz, double v2u,
+                                     int& c, float& off, float& ux, float& uy, float& uz)
+{
+    const double s = x * P.inv_dx;
+    c = int(s);
+    if (c > P.nc - 1) c = P.nc - 1;
+    if (c < 0) c = 0;
+    off = float(s - double(c));
+    if (off >= 1.0f) off = 0.99999994f;
+    ux = float(vx * v2u);
+    uy = float(vy * v2u);
+    uz = float(vz * v2u);
+}
+
+template <int S>
+__global__ __launch_bounds__(256) void k_load32(Params P, Soa32 sp, int64_t n0, double sig)
+{
+    const int64_t k = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (k >= n0) return;
+    const uint32_t stream = S == kElectron ? kStreamElectronLoad : kStreamIonLoad;
+    const U4 w = philox10(uint32_t(k), 0u, 0u, stream, P.key0, P.key1);
+    double x = unif52(w.a, w.b) * P.L;
+    if (x >= P.L) x = 0.0;
+    WordStream ws(uint32_t(k), 0u, stream, P.key0, P.key1);
+    double g0, g1, g2;
+    normal3(ws, g0, g1, g2);
+    const double v2u = 1.0 / (S == kElectron ? P.u2v_e : P.u2v_i);
+    int c;
+    float off, ux, uy, uz;
+    to32(P, x, sig * g0, sig * g1, sig * g2, v2u, c, off, ux, uy, uz);
+    sp.cell[k] = c;
+    sp.off[k] = off;
+    sp.vx[k] = ux;
+    sp.vy[k] = uy;
+    sp.vz[k] = uz;
+    sp.id[k] = uint32_t(k);
+}
+
+// leapfrog start in cell units: u -= Ef(x) / 2
+__global__ __launch_bounds__(256) void k_halfstep32(Params P, Soa32 sp, int64_t n, int S)
+{
+    const int64_t k = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (k >= n) return;
+    const float* Ef = S == kElectron ? P.Ef_e : P.Ef_i;
+    const int c = sp.cell[k];
+    const float off = sp.off[k];
+    const float e0 = Ef[c], e1 = Ef[c + 1];
+    sp.vx[k] = sp.vx[k] - 0.5f * (e0 + off * (e1 - e0));
+}
+
+// x = (cell + off) dx, v = u dx/dt (caller arrays; any may be null)
+__global__ __launch_bounds__(256) void k_to64(Params P, Soa32 src, Soa dst, int64_t n, int S)
+{
+    const int64_t k = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (k >= n) return;
+    const double u2v = S == kElectron ? P.u2v_e : P.u2v_i;
+    if (dst.x) dst.x[k] = (double(src.cell[k]) + double(src.off[k])) * P.dx;
+    if (dst.vx) dst.vx[k] = double(src.vx[k]) * u2v;
+    if (dst.vy) dst.vy[k] = double(src.vy[k]) * u2v;
+    if (dst.vz) dst.vz[k] = double(src.vz[k]) * u2v;
+    if (dst.id) dst.id[k] = src.id[k];
+}
+
+__global__ __launch_bounds__(256) void k_from64(Params P, Soa src, Soa32 dst, int64_t n, int S)
+{
+    const int64_t k = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (k >= n) return;
+    const double x = src.x[k];
+    if (!(x >= 0.0 && x < P.L)) set_err(P, kErrRange);
+    const double v2u = 1.0 / (S == kElectron ? P.u2v_e : P.u2v_i);
+    int c;
+    float off, ux, uy, uz;
+    to32(P, x, src.vx[k], src.vy[k], src.vz[k], v2u, c, off, ux, uy, uz);
+    dst.cell[k] = c;
+    dst.off[k] = off;
+    dst.vx[k] = ux;
+    dst.vy[k] = uy;
+    dst.vz[k] = uz;
+    dst.id[k] = src.id[k];
+}
+
+// FP32 field copies scaled to cells per step^2 (with the periodic ghost)
+__global__ __launch_bounds__(256) void k_scale_field(Params P)
+{
+    for (int j = threadIdx.x + blockIdx.x * blockDim.x; j <= P.nn; j += blockDim.x * gridDim.x) {
+        const double e = (P.periodic && j == P.nc) ? P.E[0] : (j < P.nn ? P.E[j] : P.E[P.nn - 1]);
+        P.Ef_e[j] = float(e * P.efs_e);
+        P.Ef_i[j] = float(e * P.efs_i);
     }
 }
 
@@ -604,27 +1066,19 @@ __device__ __forceinline__ void ionize(const Params& P, const Birth& b, uint32_t
     vi[0] = P.sig_a * g0; vi[1] = P.sig_a * g1; vi[2] = P.sig_a * g2;
 }
 
-__device__ __forceinline__ void deposit_global(const Params& P, int64_t* rho, double x)
+template <class St>
+__device__ __forceinline__ void deposit_global(const Params& P, const St& st, int64_t* rho, double xk)
 {
-    double f;
-    const int j = cell_frac(P, x, f);
-    const int64_t a = frac_units(f);
+    int64_t a;
+    const int j = key_cell(P, st, xk, a);
     int j1 = j + 1;
     if (P.periodic && j1 == P.nc) j1 = 0;
     atomicAdd((unsigned long long*)&rho[j], (unsigned long long)(kUnit - a));
     atomicAdd((unsigned long long*)&rho[j1], (unsigned long long)a);
 }
 
-__device__ __forceinline__ void move_particle(const Soa& sp, uint32_t dst, uint32_t src)
-{
-    sp.x[dst] = sp.x[src];
-    sp.vx[dst] = sp.vx[src];
-    sp.vy[dst] = sp.vy[src];
-    sp.vz[dst] = sp.vz[src];
-    sp.id[dst] = sp.id[src];
-}
-
-__global__ __launch_bounds__(kOneBlock) void k_finish(Params P, Soa se, Soa si, int64_t* rho_e,
+template <class St>
+__global__ __launch_bounds__(kOneBlock) void k_finish(Params P, St se, St si, int64_t* rho_e,
                                                       int64_t* rho_i, int64_t* zero_a, int64_t* zero_b)
 {
     __shared__ int64_t sN[2], sNH[2], sID[2], sNB, sStep;
@@ -657,6 +1111,13 @@ __global__ __launch_bounds__(kOneBlock) void k_finish(Params P, Soa se, Soa si, 
         for (int j = tid; j <= P.nn; j += T) P.E[j] = e0;
     }
     __syncthreads();
+    if (P.Ef_e != nullptr) {   // FP32 particles: field scaled to cells per step^2
+        for (int j = tid; j <= P.nn; j += T) {
+            const double e = (P.periodic && j == P.nc) ? P.E[0] : (j < P.nn ? P.E[j] : P.E[P.nn - 1]);
+            P.Ef_e[j] = float(e * P.efs_e);
+            P.Ef_i[j] = float(e * P.efs_i);
+        }
+    }
     const uint32_t step = uint32_t(sStep);
     int64_t nb = sNB < P.max_births ? sNB : P.max_births;
     int64_t nh[2], Np[2];
@@ -690,11 +1151,9 @@ __global__ __launch_bounds__(kOneBlock) void k_finish(Params P, Soa se, Soa si, 
                 const Birth b = P.births[k];
                 double vs[3];
                 ionize(P, b, step, vs, bve[m], bvi[m]);
-                se.vx[b.slot] = vs[0];
-                se.vy[b.slot] = vs[1];
-                se.vz[b.slot] = vs[2];
-                deposit_global(P, rho_e, b.x);
-                deposit_global(P, rho_i, b.x);
+                store_v(P, se, b.slot, kElectron, vs[0], vs[1], vs[2]);
+                deposit_global(P, se, rho_e, b.x);
+                deposit_global(P, si, rho_i, b.x);
                 sPid[k] = b.pid;
                 bpid[m] = b.pid;
                 bx[m] = b.x;
@@ -705,11 +1164,9 @@ __global__ __launch_bounds__(kOneBlock) void k_finish(Params P, Soa se, Soa si, 
             const Birth b = P.births[k];
             double vs[3], ve[3], vi[3];
             ionize(P, b, step, vs, ve, vi);
-            se.vx[b.slot] = vs[0];
-            se.vy[b.slot] = vs[1];
-            se.vz[b.slot] = vs[2];
-            deposit_global(P, rho_e, b.x);
-            deposit_global(P, rho_i, b.x);
+            store_v(P, se, b.slot, kElectron, vs[0], vs[1], vs[2]);
+            deposit_global(P, se, rho_e, b.x);
+            deposit_global(P, si, rho_i, b.x);
         }
     }
     // 3. hole filling from the tail [Np, N): small lists in LDS
@@ -734,13 +1191,13 @@ __global__ __launch_bounds__(kOneBlock) void k_finish(Params P, Soa se, Soa si, 
     __syncthreads();
     for (int s = 0; s < 2; ++s) {
         if (!lds[s] || nh[s] == 0) continue;
-        const Soa sp = s == 0 ? se : si;
+        const St sp = s == 0 ? se : si;
         for (unsigned int k = tid; k < sC[2 * s]; k += T) move_particle(sp, sL1[s][k], sL2[s][k]);
     }
     // large hole lists: the same algorithm on global scratch, one species at a time
     for (int s = 0; s < 2; ++s) {
         if (lds[s] || nh[s] == 0) continue;
-        const Soa sp = s == 0 ? se : si;
+        const St sp = s == 0 ? se : si;
         const int64_t words = (nh[s] + 31) >> 5;
         if (tid == 0) { sC[0] = 0u; sC[1] = 0u; }
         for (int64_t k = tid; k < words; k += T) P.bitmap[k] = 0u;
@@ -774,11 +1231,8 @@ __global__ __launch_bounds__(kOneBlock) void k_finish(Params P, Soa se, Soa si, 
             if (k < nb) {
                 int64_t r = 0;
                 for (int64_t q = 0; q < nb; ++q) r += sPid[q] < bpid[m] ? 1 : 0;
-                const int64_t pe = Np[0] + r, pi = Np[1] + r;
-                se.x[pe] = bx[m]; se.vx[pe] = bve[m][0]; se.vy[pe] = bve[m][1]; se.vz[pe] = bve[m][2];
-                se.id[pe] = uint32_t(sID[0] + r);
-                si.x[pi] = bx[m]; si.vx[pi] = bvi[m][0]; si.vy[pi] = bvi[m][1]; si.vz[pi] = bvi[m][2];
-                si.id[pi] = uint32_t(sID[1] + r);
+                put_particle(P, se, Np[0] + r, kElectron, bx[m], bve[m], uint32_t(sID[0] + r));
+                put_particle(P, si, Np[1] + r, kIon, bx[m], bvi[m], uint32_t(sID[1] + r));
             }
         }
     } else {
@@ -788,11 +1242,8 @@ __global__ __launch_bounds__(kOneBlock) void k_finish(Params P, Soa se, Soa si, 
             ionize(P, b, step, vs, ve, vi);
             int64_t r = 0;
             for (int64_t q = 0; q < nb; ++q) r += P.births[q].pid < b.pid ? 1 : 0;
-            const int64_t pe = Np[0] + r, pi = Np[1] + r;
-            se.x[pe] = b.x; se.vx[pe] = ve[0]; se.vy[pe] = ve[1]; se.vz[pe] = ve[2];
-            se.id[pe] = uint32_t(sID[0] + r);
-            si.x[pi] = b.x; si.vx[pi] = vi[0]; si.vy[pi] = vi[1]; si.vz[pi] = vi[2];
-            si.id[pi] = uint32_t(sID[1] + r);
+            put_particle(P, se, Np[0] + r, kElectron, b.x, ve, uint32_t(sID[0] + r));
+            put_particle(P, si, Np[1] + r, kIon, b.x, vi, uint32_t(sID[1] + r));
         }
     }
     __threadfence();
@@ -866,6 +1317,19 @@ __global__ __launch_bounds__(256) void k_deposit(Params P, const double* x, int6
     atomicAdd((unsigned long long*)&rho[j1], (unsigned long long)a);
 }
 
+// deposit of an FP32 store (rho cleared beforehand), same weights as the push
+__global__ __launch_bounds__(256) void k_deposit32(Params P, Soa32 sp, int64_t n, int64_t* rho)
+{
+    const int64_t k = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (k >= n) return;
+    const int j = sp.cell[k];
+    const int64_t a = frac_units32(sp.off[k]);
+    int j1 = j + 1;
+    if (P.periodic && j1 == P.nc) j1 = 0;
+    atomicAdd((unsigned long long*)&rho[j], (unsigned long long)(kUnit - a));
+    atomicAdd((unsigned long long*)&rho[j1], (unsigned long long)a);
+}
+
 __global__ void k_fill_i64(int64_t* p, int64_t n, int64_t v)
 {
     const int64_t k = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
@@ -884,15 +1348,16 @@ __global__ void k_copy_soa(Soa dst, Soa src, int64_t n)
 }
 
 // ----------------------------------------------------------------- moments
-__global__ __launch_bounds__(256) void k_moments_e(Params P, Soa sp, int32_t cpg, int64_t* out)
+template <class St>
+__global__ __launch_bounds__(256) void k_moments_e(Params P, St sp, int32_t cpg, int64_t* out)
 {
     const int64_t n = P.cnt->n[0];
     const int nc = P.nc;
     for (int64_t k = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; k < n;
          k += int64_t(gridDim.x) * blockDim.x) {
-        double f;
-        const int j = cell_frac(P, sp.x[k], f);
-        const double vx = sp.vx[k], vy = sp.vy[k], vz = sp.vz[k];
+        const int j = cell_at(P, sp, k);
+        double vx, vy, vz;
+        load_v(P, sp, uint32_t(k), kElectron, vx, vy, vz);
         const double eps = P.c_eps * ((vx * vx + vy * vy) + vz * vz);
         atomicAdd((unsigned long long*)&out[j], 1ull);
         atomicAdd((unsigned long long*)&out[nc + j], (unsigned long long)int64_t(eps * 1048576.0));
@@ -903,16 +1368,18 @@ __global__ __launch_bounds__(256) void k_moments_e(Params P, Soa sp, int32_t cpg
     }
 }
 
-__global__ __launch_bounds__(256) void k_moments_i(Params P, Soa sp, int64_t* out, int reset)
+template <class St>
+__global__ __launch_bounds__(256) void k_moments_i(Params P, St sp, int64_t* out, int reset)
 {
     const int64_t n = P.cnt->n[1];
     const int nc = P.nc;
     for (int64_t k = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; k < n;
          k += int64_t(gridDim.x) * blockDim.x) {
-        double f;
-        const int j = cell_frac(P, sp.x[k], f);
+        const int j = cell_at(P, sp, k);
+        double vx, vy, vz;
+        load_v(P, sp, uint32_t(k), kIon, vx, vy, vz);
         atomicAdd((unsigned long long*)&out[4 * nc + j], 1ull);
-        atomicAdd((unsigned long long*)&out[5 * nc + j], (unsigned long long)int64_t(sp.vx[k] * 1024.0));
+        atomicAdd((unsigned long long*)&out[5 * nc + j], (unsigned long long)int64_t(vx * 1024.0));
     }
     if (blockIdx.x == 0) {
         for (int j = threadIdx.x; j < nc; j += blockDim.x) {
@@ -964,7 +1431,8 @@ __device__ __forceinline__ void count_wave(int* cw, int wbase, int32_t* glob, bo
     }
 }
 
-__global__ __launch_bounds__(256) void k_sort_count(Params P, Soa sp, int S)
+template <class St>
+__global__ __launch_bounds__(256) void k_sort_count(Params P, St sp, int S)
 {
     __shared__ int cw[kWindow];
     const int64_t n = P.cnt->n[S];
@@ -972,17 +1440,12 @@ __global__ __launch_bounds__(256) void k_sort_count(Params P, Soa sp, int S)
     block_chunk(n, beg, end);
     if (beg >= end) return;
     for (int k = threadIdx.x; k < kWindow; k += blockDim.x) cw[k] = 0;
-    double f0;
-    const int wbase = cell_frac(P, sp.x[beg], f0) - kHalo;
+    const int wbase = cell_at(P, sp, beg) - kHalo;
     __syncthreads();
     for (int64_t i0 = beg; i0 < end; i0 += blockDim.x) {
         const int64_t i = i0 + threadIdx.x;
         const bool act = i < end;
-        int c = 0;
-        if (act) {
-            double f;
-            c = cell_frac(P, sp.x[i], f);
-        }
+        const int c = act ? cell_at(P, sp, i) : 0;
         count_wave(cw, wbase, P.sort_cnt, act, c);
     }
     __syncthreads();
@@ -1015,7 +1478,8 @@ __global__ __launch_bounds__(kOneBlock) void k_sort_scan(Params P)
     }
 }
 
-__global__ __launch_bounds__(256) void k_sort_scatter(Params P, Soa src, Soa dst, int S)
+template <class St>
+__global__ __launch_bounds__(256) void k_sort_scatter(Params P, St src, St dst, int S)
 {
     __shared__ int cw[kWindow];
     __shared__ int bw[kWindow];
@@ -1024,18 +1488,13 @@ __global__ __launch_bounds__(256) void k_sort_scatter(Params P, Soa src, Soa dst
     block_chunk(n, beg, end);
     if (beg >= end) return;
     for (int k = threadIdx.x; k < kWindow; k += blockDim.x) cw[k] = 0;
-    double f0;
-    const int wbase = cell_frac(P, src.x[beg], f0) - kHalo;
+    const int wbase = cell_at(P, src, beg) - kHalo;
     __syncthreads();
     // pass 1: in-window counts of this chunk
     for (int64_t i0 = beg; i0 < end; i0 += blockDim.x) {
         const int64_t i = i0 + threadIdx.x;
         const bool act = i < end;
-        int c = 0;
-        if (act) {
-            double f;
-            c = cell_frac(P, src.x[i], f);
-        }
+        const int c = act ? cell_at(P, src, i) : 0;
         count_wave(cw, wbase, nullptr, act, c);
     }
     __syncthreads();
@@ -1051,11 +1510,7 @@ __global__ __launch_bounds__(256) void k_sort_scatter(Params P, Soa src, Soa dst
     for (int64_t i0 = beg; i0 < end; i0 += blockDim.x) {
         const int64_t i = i0 + threadIdx.x;
         const bool act = i < end;
-        int c = 0;
-        if (act) {
-            double f;
-            c = cell_frac(P, src.x[i], f);
-        }
+        const int c = act ? cell_at(P, src, i) : 0;
         int pos = 0;
         bool pend = act;
 #pragma unroll
@@ -1082,13 +1537,7 @@ __global__ __launch_bounds__(256) void k_sort_scatter(Params P, Soa src, Soa dst
             if (li >= 0 && li < kWindow) pos = bw[li] + atomicAdd(&cw[li], 1);
             else pos = atomicAdd(&P.sort_off[c], 1);
         }
-        if (act) {
-            dst.x[pos] = src.x[i];
-            dst.vx[pos] = src.vx[i];
-            dst.vy[pos] = src.vy[i];
-            dst.vz[pos] = src.vz[i];
-            dst.id[pos] = src.id[i];
-        }
+        if (act) copy_particle(dst, pos, src, i);
     }
 }
 
@@ -1120,17 +1569,49 @@ hipError_t advance(const Params& P, int species, const Soa& sp, int64_t* rho, ui
     return hipGetLastError();
 }
 
+hipError_t advance(const Params& P, int species, const Soa32& sp, int64_t* rho, uint8_t* ev, int64_t evlen,
+                   int grid, hipStream_t st)
+{
+    const bool e = ev != nullptr;
+    if (species == kElectron) {
+        if (e) hipLaunchKernelGGL(k_push_e32<true>, dim3(grid), dim3(kAdvBlock), 0, st, P, sp, rho, ev, evlen);
+        else hipLaunchKernelGGL(k_push_e32<false>, dim3(grid), dim3(kAdvBlock), 0, st, P, sp, rho, ev, evlen);
+    } else {
+        if (e) hipLaunchKernelGGL(k_advance_i32<true>, dim3(grid), dim3(kAdvBlock), 0, st, P, sp, rho, ev, evlen);
+        else hipLaunchKernelGGL(k_advance_i32<false>, dim3(grid), dim3(kAdvBlock), 0, st, P, sp, rho, ev, evlen);
+    }
+    return hipGetLastError();
+}
+
+template <class St>
+static hipError_t finish_t(const Params& P, const St& se, const St& si, int64_t* rho_e, int64_t* rho_i,
+                           int64_t* zero_a, int64_t* zero_b, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_finish<St>, dim3(1), dim3(kOneBlock), 0, st, P, se, si, rho_e, rho_i, zero_a, zero_b);
+    return hipGetLastError();
+}
 hipError_t finish(const Params& P, const Soa& se, const Soa& si, int64_t* rho_e, int64_t* rho_i,
                   int64_t* zero_a, int64_t* zero_b, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_finish, dim3(1), dim3(kOneBlock), 0, st, P, se, si, rho_e, rho_i, zero_a, zero_b);
-    return hipGetLastError();
+    return finish_t(P, se, si, rho_e, rho_i, zero_a, zero_b, st);
+}
+hipError_t finish(const Params& P, const Soa32& se, const Soa32& si, int64_t* rho_e, int64_t* rho_i,
+                  int64_t* zero_a, int64_t* zero_b, hipStream_t st)
+{
+    return finish_t(P, se, si, rho_e, rho_i, zero_a, zero_b, st);
 }
 
 hipError_t field(const Params& P, const int64_t* rho_e, const int64_t* rho_i, double* E, double* phi,
                  int ghost, hipStream_t st)
 {
     hipLaunchKernelGGL(k_field, dim3(1), dim3(kOneBlock), 0, st, P, rho_e, rho_i, E, phi, ghost);
+    return hipGetLastError();
+}
+
+hipError_t scale_field(const Params& P, hipStream_t st)
+{
+    if (P.Ef_e == nullptr) return hipSuccess;
+    hipLaunchKernelGGL(k_scale_field, dim3(32), dim3(256), 0, st, P);
     return hipGetLastError();
 }
 
@@ -1145,10 +1626,42 @@ hipError_t load(const Params& P, int species, const Soa& sp, int64_t n0, double 
     return hipGetLastError();
 }
 
+hipError_t load(const Params& P, int species, const Soa32& sp, int64_t n0, double sig, hipStream_t st)
+{
+    const int g = grid_for(n0, 256, 1 << 30);
+    if (n0 == 0) return hipSuccess;
+    if (species == kElectron)
+        hipLaunchKernelGGL(k_load32<kElectron>, dim3(g), dim3(256), 0, st, P, sp, n0, sig);
+    else
+        hipLaunchKernelGGL(k_load32<kIon>, dim3(g), dim3(256), 0, st, P, sp, n0, sig);
+    return hipGetLastError();
+}
+
 hipError_t halfstep(const Params& P, const Soa& sp, int64_t n, double hq, hipStream_t st)
 {
     if (n == 0) return hipSuccess;
     hipLaunchKernelGGL(k_halfstep, dim3(grid_for(n, 256, 1 << 30)), dim3(256), 0, st, P, sp, n, hq);
+    return hipGetLastError();
+}
+
+hipError_t halfstep(const Params& P, const Soa32& sp, int species, int64_t n, hipStream_t st)
+{
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_halfstep32, dim3(grid_for(n, 256, 1 << 30)), dim3(256), 0, st, P, sp, n, species);
+    return hipGetLastError();
+}
+
+hipError_t to64(const Params& P, const Soa32& src, const Soa& dst, int64_t n, int species, hipStream_t st)
+{
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_to64, dim3(grid_for(n, 256, 1 << 30)), dim3(256), 0, st, P, src, dst, n, species);
+    return hipGetLastError();
+}
+
+hipError_t from64(const Params& P, const Soa& src, const Soa32& dst, int64_t n, int species, hipStream_t st)
+{
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_from64, dim3(grid_for(n, 256, 1 << 30)), dim3(256), 0, st, P, src, dst, n, species);
     return hipGetLastError();
 }
 
@@ -1167,6 +1680,14 @@ hipError_t deposit(const Params& P, const double* x, int64_t n, int64_t* rho, hi
     return hipGetLastError();
 }
 
+hipError_t deposit(const Params& P, const Soa32& sp, int64_t n, int64_t* rho, hipStream_t st)
+{
+    hipError_t e = fill_i64(rho, P.nn, 0, st);
+    if (e != hipSuccess || n == 0) return e;
+    hipLaunchKernelGGL(k_deposit32, dim3(grid_for(n, 256, 1 << 30)), dim3(256), 0, st, P, sp, n, rho);
+    return hipGetLastError();
+}
+
 hipError_t copy_soa(const Soa& dst, const Soa& src, int64_t n, hipStream_t st)
 {
     if (n == 0) return hipSuccess;
@@ -1174,23 +1695,43 @@ hipError_t copy_soa(const Soa& dst, const Soa& src, int64_t n, hipStream_t st)
     return hipGetLastError();
 }
 
-hipError_t moments(const Params& P, const Soa& se, const Soa& si, int32_t cpg, int reset, int64_t* out,
-                   int64_t out_len, hipStream_t st)
+template <class St>
+static hipError_t moments_t(const Params& P, const St& se, const St& si, int32_t cpg, int reset, int64_t* out,
+                            int64_t out_len, hipStream_t st)
 {
     hipError_t e = fill_i64(out, out_len, 0, st);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_moments_e, dim3(1024), dim3(256), 0, st, P, se, cpg, out);
-    hipLaunchKernelGGL(k_moments_i, dim3(1024), dim3(256), 0, st, P, si, out, reset);
+    hipLaunchKernelGGL(k_moments_e<St>, dim3(1024), dim3(256), 0, st, P, se, cpg, out);
+    hipLaunchKernelGGL(k_moments_i<St>, dim3(1024), dim3(256), 0, st, P, si, out, reset);
     if (reset) hipLaunchKernelGGL(k_reset_iz, dim3(64), dim3(256), 0, st, P);
     return hipGetLastError();
 }
+hipError_t moments(const Params& P, const Soa& se, const Soa& si, int32_t cpg, int reset, int64_t* out,
+                   int64_t out_len, hipStream_t st)
+{
+    return moments_t(P, se, si, cpg, reset, out, out_len, st);
+}
+hipError_t moments(const Params& P, const Soa32& se, const Soa32& si, int32_t cpg, int reset, int64_t* out,
+                   int64_t out_len, hipStream_t st)
+{
+    return moments_t(P, se, si, cpg, reset, out, out_len, st);
+}
 
+template <class St>
+static hipError_t sort_t(const Params& P, int species, const St& src, const St& dst, int grid, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_sort_count<St>, dim3(grid), dim3(256), 0, st, P, src, species);
+    hipLaunchKernelGGL(k_sort_scan, dim3(1), dim3(kOneBlock), 0, st, P);
+    hipLaunchKernelGGL(k_sort_scatter<St>, dim3(grid), dim3(256), 0, st, P, src, dst, species);
+    return hipGetLastError();
+}
 hipError_t sort(const Params& P, int species, const Soa& src, const Soa& dst, int grid, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_sort_count, dim3(grid), dim3(256), 0, st, P, src, species);
-    hipLaunchKernelGGL(k_sort_scan, dim3(1), dim3(kOneBlock), 0, st, P);
-    hipLaunchKernelGGL(k_sort_scatter, dim3(grid), dim3(256), 0, st, P, src, dst, species);
-    return hipGetLastError();
+    return sort_t(P, species, src, dst, grid, st);
+}
+hipError_t sort(const Params& P, int species, const Soa32& src, const Soa32& dst, int grid, hipStream_t st)
+{
+    return sort_t(P, species, src, dst, grid, st);
 }
 
 int max_nodes() { return kOneBlock * kMaxSeg; }

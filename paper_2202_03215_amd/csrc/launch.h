@@ -5,21 +5,35 @@
 namespace pclaunch {
 using pcdev::Params;
 using pcdev::Soa;
+using pcdev::Soa32;
 
 hipError_t advance(const Params& P, int species, const Soa& sp, int64_t* rho, uint8_t* ev, int64_t evlen,
                    int grid, hipStream_t st);
+hipError_t advance(const Params& P, int species, const Soa32& sp, int64_t* rho, uint8_t* ev, int64_t evlen,
+                   int grid, hipStream_t st);
 hipError_t finish(const Params& P, const Soa& se, const Soa& si, int64_t* rho_e, int64_t* rho_i,
+                  int64_t* zero_a, int64_t* zero_b, hipStream_t st);
+hipError_t finish(const Params& P, const Soa32& se, const Soa32& si, int64_t* rho_e, int64_t* rho_i,
                   int64_t* zero_a, int64_t* zero_b, hipStream_t st);
 hipError_t field(const Params& P, const int64_t* rho_e, const int64_t* rho_i, double* E, double* phi,
                  int ghost, hipStream_t st);
+hipError_t scale_field(const Params& P, hipStream_t st);
 hipError_t load(const Params& P, int species, const Soa& sp, int64_t n0, double sig, hipStream_t st);
+hipError_t load(const Params& P, int species, const Soa32& sp, int64_t n0, double sig, hipStream_t st);
 hipError_t halfstep(const Params& P, const Soa& sp, int64_t n, double hq, hipStream_t st);
+hipError_t halfstep(const Params& P, const Soa32& sp, int species, int64_t n, hipStream_t st);
+hipError_t to64(const Params& P, const Soa32& src, const Soa& dst, int64_t n, int species, hipStream_t st);
+hipError_t from64(const Params& P, const Soa& src, const Soa32& dst, int64_t n, int species, hipStream_t st);
 hipError_t fill_i64(int64_t* p, int64_t n, int64_t v, hipStream_t st);
 hipError_t deposit(const Params& P, const double* x, int64_t n, int64_t* rho, hipStream_t st);
+hipError_t deposit(const Params& P, const Soa32& sp, int64_t n, int64_t* rho, hipStream_t st);
 hipError_t copy_soa(const Soa& dst, const Soa& src, int64_t n, hipStream_t st);
 hipError_t moments(const Params& P, const Soa& se, const Soa& si, int32_t cpg, int reset, int64_t* out,
                    int64_t out_len, hipStream_t st);
+hipError_t moments(const Params& P, const Soa32& se, const Soa32& si, int32_t cpg, int reset, int64_t* out,
+                   int64_t out_len, hipStream_t st);
 hipError_t sort(const Params& P, int species, const Soa& src, const Soa& dst, int grid, hipStream_t st);
+hipError_t sort(const Params& P, int species, const Soa32& src, const Soa32& dst, int grid, hipStream_t st);
 int max_nodes();
 
 }  // namespace pclaunch

@@ -37,7 +37,7 @@ class PcError(RuntimeError):
 class pc_config(C.Structure):
     _fields_ = [(k, C.c_int32) for k in ("bc", "n_cells", "ppc", "ion_subcycle", "wall_mode",
                                          "energy_sharing", "poisson", "sort_interval",
-                                         "launch_blocks", "pad0", "pad1", "pad2")] + \
+                                         "launch_blocks", "precision", "pad1", "pad2")] + \
         [(k, C.c_double) for k in ("L", "V", "p_torr", "Tg", "n0", "Te0_eV", "Ti0_K", "nu_w",
                                    "dt", "eps_cap", "g_cap", "capacity", "M_amu", "el_A",
                                    "el_B", "el_p", "ex_U", "ex_smax", "iz_U", "iz_smax",
@@ -119,6 +119,7 @@ def make_config(cfg: dict) -> pc_config:
     s.poisson = int(cfg["poisson"])
     s.sort_interval = int(cfg.get("sort_interval", 0))
     s.launch_blocks = int(cfg.get("launch_blocks", 0))
+    s.precision = {"fp64": 0, "fp32": 1}[cfg.get("precision", "fp64")]
     for k in ("L", "V", "p_torr", "Tg", "n0", "Te0_eV", "Ti0_K", "nu_w", "dt", "eps_cap",
               "g_cap", "M_amu", "el_A", "el_B", "el_p", "ex_U", "ex_smax", "iz_U", "iz_smax",
               "cx_sigma", "opb_w"):

@@ -1,0 +1,138 @@
+"""FP32 particle path (cell-relative FP32 state and push; field solve and
+collision arithmetic in FP64) against the FP64 oracle.
+
+Per step from a shared state the differences come only from FP32 rounding of
+the offset within a cell (ulp 6e-8 cell) and of velocities (relative 6e-8 per
+operation): positions agree to 1e-6 cell, velocities to 1e-6 (|v| + v_th),
+and every event agrees except draws within rounding of a threshold (counted;
+at most 1e-4 of the particles).  Charges agree to a few units of 2^-25 per
+particle; the total charge is exact.  Free runs are compared statistically
+with the FP64 GPU path.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle.pco import Oracle
+from tests.gpu_helpers import ELECTRON, ION, by_id, copy_gpu_to_oracle, gpu_state
+
+pytestmark = pytest.mark.gpu
+
+QE = 1.602176634e-19
+ME = 9.1093837015e-31
+AMU = 1.66053906660e-27
+KB = 1.380649e-23
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+def _column(cfg):
+    from paper_2202_03215_amd.column import Column
+    return Column(cfg)
+
+
+def _vth(cfg):
+    return (math.sqrt(max(cfg["Te0_eV"], 1.0) * QE / ME),
+            math.sqrt(KB * cfg["Tg"] / (cfg["M_amu"] * AMU)))
+
+
+def _step_parity(cfg, steps):
+    col = _column(cfg)
+    orc = Oracle(cfg, init=False)
+    ev_e, ev_i = col.set_events(4 * col.capacity, 4 * col.capacity)
+    dx = cfg["L"] / cfg["n_cells"]
+    vth = _vth(cfg)
+    flips = 0
+    total = 0
+    for k in range(steps):
+        copy_gpu_to_oracle(col, orc)
+        ev_e.zero_()
+        ev_i.zero_()
+        col.step(1)
+        orc.step(1)
+        c = col.counts()
+        assert c["errors"] == 0 and orc.errors == 0
+        for s, ev in ((ELECTRON, ev_e), (ION, ev_i)):
+            n = orc.next_id(s)
+            ge = ev[:n].cpu().numpy()
+            oe = orc.events(s, n)
+            flips += int((ge != oe).sum())
+            total += n
+        if c["n"] != (orc.count(0), orc.count(1)):
+            continue       # a threshold flip changed the population this step
+        for s in (ELECTRON, ION):
+            g = gpu_state(col, s)
+            o = by_id(orc.state(s))
+            if not np.array_equal(g[4], o[4]):
+                continue
+            d = np.abs(g[0] - o[0])
+            d = np.minimum(d, cfg["L"] - d) if cfg["bc"] == "periodic" else d
+            assert d.max() <= 1e-6 * dx, (k, s, d.max() / dx)
+            for q in (1, 2, 3):
+                rel = np.abs(g[q] - o[q]) / (np.abs(o[q]) + vth[s])
+                assert rel.max() <= 1e-6, (k, s, q, rel.max())
+        Eg, reg, rig = col.get_field()
+        Eo, reo, rio = orc.field()
+        reg, rig = reg.cpu().numpy(), rig.cpu().numpy()
+        assert reg.sum() == reo.sum() and rig.sum() == rio.sum()
+        assert np.abs(reg - reo).max() <= 64 * (1 + reo.max() // (1 << 25))
+        assert np.abs(rig - rio).max() <= 64 * (1 + rio.max() // (1 << 25))
+    assert flips <= max(2, 1e-4 * total), flips
+    return flips
+
+
+def test_fp32_step_parity_bounded(torch_cuda):
+    _step_parity(W.with_(W.small_bounded(), precision="fp32"), steps=40)
+
+
+def test_fp32_step_parity_periodic_ionizing(torch_cuda):
+    cfg = W.tiny("periodic", n_cells=101, L=0.0101, V=0.0101 * 6.0e3, ppc=40, Te0_eV=8.0,
+                 nu_w=2e8, eps_cap=100.0, sort_interval=3, precision="fp32")
+    _step_parity(cfg, steps=45)
+
+
+def test_fp32_initial_load_matches_fp64(torch_cuda):
+    cfg = W.tiny("periodic", n_cells=200, L=0.02, V=2.0, ppc=50)
+    a = _column(cfg)
+    b = _column(W.with_(cfg, precision="fp32"))
+    dx = cfg["L"] / cfg["n_cells"]
+    for s in (ELECTRON, ION):
+        ga, gb = gpu_state(a, s), gpu_state(b, s)
+        assert np.array_equal(ga[4], gb[4])
+        assert np.abs(ga[0] - gb[0]).max() <= 1e-6 * dx
+        for q in (1, 2, 3):
+            assert np.abs(ga[q] - gb[q]).max() <= 1e-6 * np.abs(ga[q]).max()
+
+
+def test_fp32_free_run_statistics_match_fp64(torch_cuda):
+    # free runs diverge after the first rounding difference; compare the
+    # state statistically after 600 steps (EEDF, mean energy, density profile)
+    from paper_2202_03215_amd import analysis as A
+    cfg = W.tiny("periodic", n_cells=400, L=0.04, V=0.04 * 1000.0, ppc=200, n0=1e15,
+                 Te0_eV=4.0, sort_interval=10)
+    out = {}
+    for prec in ("fp64", "fp32"):
+        col = _column(W.with_(cfg, precision=prec))
+        col.step(600)
+        assert col.counts()["errors"] == 0
+        m = A.split(col.moments(cells_per_group=400).cpu().numpy(), 400, 400)
+        out[prec] = m
+    a, b = out["fp64"], out["fp32"]
+    ea = a["eps"].sum() / a["ne"].sum() / A.EPS_SCALE
+    eb = b["eps"].sum() / b["ne"].sum() / A.EPS_SCALE
+    assert abs(eb / ea - 1) < 0.01
+    fa = a["eepf"][0] / a["eepf"][0].sum()
+    fb = b["eepf"][0] / b["eepf"][0].sum()
+    assert np.abs(fa - fb).sum() < 0.03
+    # density profile: 400 cells x 200 particles; compare 20-cell averages
+    na = a["ne"].reshape(20, 20).sum(axis=1) / 4000.0
+    nb = b["ne"].reshape(20, 20).sum(axis=1) / 4000.0
+    assert np.abs(na - nb).max() < 0.08

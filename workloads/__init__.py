@@ -32,6 +32,7 @@ Config keys (all SI unless noted):
   poisson       1 = self-consistent field, 0 = imposed field only (swarm mode)
   sort_interval steps between counting sorts (0 = never; no effect on physics)
   capacity      particle-array capacity as a multiple of the initial count
+  precision     "fp64" | "fp32" particle state on the GPU (the oracle is FP64)
   seed          Philox key
 """
 from __future__ import annotations
