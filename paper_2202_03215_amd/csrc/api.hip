@@ -166,7 +166,8 @@ pc_status derive(const pc_config* c, Derived* d)
     const double capf = c->capacity > 1.0 ? c->capacity : 1.0;
     int64_t cap = int64_t(std::ceil(double(d->n0) * capf));
     cap = std::max<int64_t>(1024, (cap + 255) & ~int64_t(255));
-    if (cap >= (int64_t(1) << 31)) return fail(PC_ERR_INVALID_ARG, "capacity above 2^31 particles");
+    // particle arrays are addressed with 32-bit byte offsets (8-byte fields)
+    if (cap > (int64_t(1) << 29)) return fail(PC_ERR_INVALID_ARG, "capacity above 2^29 particles");
     d->cap = cap;
     d->max_births = std::max<int64_t>(4096, cap / 256);
     d->max_holes = std::max<int64_t>(8192, cap / 64);

@@ -239,10 +239,13 @@ __device__ __forceinline__ int cell_frac(const Params& P, double x, double& f)
     return j;
 }
 
+// 25-bit weight of a cell fraction f in [0, 1]: trunc(f 2^25), at most 2^25.
+// f 2^25 < 2^32, so the unsigned 32-bit conversion truncates exactly as a
+// 64-bit one would, in one instruction.
 __device__ __forceinline__ int64_t frac_units(double f)
 {
-    int64_t a = int64_t(f * kUnitD);
-    return a > kUnit ? kUnit : a;
+    const uint32_t a = uint32_t(f * kUnitD);
+    return int64_t(a > uint32_t(kUnit) ? uint32_t(kUnit) : a);
 }
 
 }  // namespace pcdev

@@ -33,11 +33,14 @@ __device__ __forceinline__ void set_err(const Params& P, uint32_t bits) { atomic
 __device__ __forceinline__ void add_node(unsigned long long* win, int wbase, int64_t* rho, int node,
                                          int64_t v)
 {
-    const int li = node - wbase;
-    if (li >= 0 && li < kWindow)
-        atomicAdd(&win[li], (unsigned long long)v);
+    // distinct scopes keep the two adds apart (an LDS add and a global add,
+    // rather than one flat atomic through a selected address)
+    const uint32_t li = uint32_t(node - wbase);
+    if (li < uint32_t(kWindow))
+        __hip_atomic_fetch_add(&win[li], (unsigned long long)v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
     else
-        atomicAdd((unsigned long long*)&rho[node], (unsigned long long)v);
+        __hip_atomic_fetch_add((unsigned long long*)&rho[node], (unsigned long long)v, __ATOMIC_RELAXED,
+                               __HIP_MEMORY_SCOPE_AGENT);
 }
 
 // Wave-aggregated CIC deposit.  The wave's two leading cells (those of the
@@ -122,6 +125,31 @@ __device__ __forceinline__ void block_chunk(int64_t n, int64_t& beg, int64_t& en
     const int64_t per = ((n + gridDim.x - 1) / gridDim.x + 63) & ~int64_t(63);
     beg = int64_t(blockIdx.x) * per;
     end = beg + per < n ? beg + per : n;
+}
+
+// Global access through a wave-uniform base and a 32-bit byte offset (each
+// particle field stays below 4 GiB: capacity <= 2^29), which selects the
+// scalar-base form of the vector load and store instructions instead of
+// per-lane 64-bit address arithmetic.
+template <typename T>
+__device__ __forceinline__ T ld32(const T* __restrict__ base, uint32_t i)
+{
+    return *(const T*)((const char*)base + i * uint32_t(sizeof(T)));
+}
+template <typename T>
+__device__ __forceinline__ void st32(T* __restrict__ base, uint32_t i, T v)
+{
+    *(T*)((char*)base + i * uint32_t(sizeof(T))) = v;
+}
+
+// Philox key words reloaded inside a particle loop: the empty asm makes them
+// loop-variant, so the ten round keys are rebuilt with scalar adds in each
+// iteration instead of being held (and spilled) across the loop.
+__device__ __forceinline__ void loop_keys(const Params& P, uint32_t& k0, uint32_t& k1)
+{
+    k0 = P.key0;
+    k1 = P.key1;
+    asm volatile("" : "+s"(k0), "+s"(k1));
 }
 
 // periodic reinjection / absorbing walls; returns false if the particle left
@@ -370,50 +398,54 @@ __global__ __launch_bounds__(kAdvBlock) void k_push_e(Params P, Soa sp, int64_t*
     // software pipeline: the next tile's loads are issued before this tile's work
     double px = 0.0, pvx = 0.0;
     uint32_t pid = 0;
+    const uint32_t ue = uint32_t(end);
     {
-        const int64_t i = beg + threadIdx.x;
-        if (i < end) {
-            px = sp.x[i];
-            pvx = sp.vx[i];
-            pid = sp.id[i];
+        const uint32_t i = uint32_t(beg) + threadIdx.x;
+        if (i < ue) {
+            px = ld32(sp.x, i);
+            pvx = ld32(sp.vx, i);
+            pid = ld32(sp.id, i);
         }
     }
-    for (int64_t i0 = beg; i0 < end; i0 += kAdvBlock) {
-        const int64_t i = i0 + threadIdx.x;
-        const bool act = i < end;
+    for (uint32_t i0 = uint32_t(beg); i0 < ue; i0 += kAdvBlock) {
+        const uint32_t i = i0 + threadIdx.x;
+        const bool act = i < ue;
         bool alive = false, cand = false;
         int jn = 0;
         int64_t an = 0;
         uint2 wcd = make_uint2(0u, 0u);
         double x = px, vx = pvx;
         const uint32_t id = pid;
-        if (i + kAdvBlock < end) {
-            px = sp.x[i + kAdvBlock];
-            pvx = sp.vx[i + kAdvBlock];
-            pid = sp.id[i + kAdvBlock];
+        if (i + kAdvBlock < ue) {
+            px = ld32(sp.x, i + kAdvBlock);
+            pvx = ld32(sp.vx, i + kAdvBlock);
+            pid = ld32(sp.id, i + kAdvBlock);
         }
         if (act) {
             double f;
             const int j = cell_frac(P, x, f);
-            const double Ex = E[j] + f * (E[j + 1] - E[j]);
+            const double e0 = ld32(E, uint32_t(j)), e1 = ld32(E, uint32_t(j) + 1u);
+            const double Ex = e0 + f * (e1 - e0);
             vx = vx + P.qmdt_e * Ex;
             x = x + vx * P.dt;
             uint8_t code = kEvNone;
             alive = apply_boundary(P, x, code);
             if (alive) {
-                const U4 w = philox10(id, step, 0u, kStreamElectronStep, P.key0, P.key1);
-                const uint64_t k0 = draw52(w.a, w.b);
-                if (k0 >= P.kw_e) {
+                uint32_t k0, k1;
+                loop_keys(P, k0, k1);
+                const U4 w = philox10(id, step, 0u, kStreamElectronStep, k0, k1);
+                const uint64_t k = draw52(w.a, w.b);
+                if (k >= P.kw_e) {
                     alive = false;
                     code = kEvWall;
                 } else {
-                    cand = k0 < P.kn_e;
+                    cand = k < P.kn_e;
                 }
                 wcd = make_uint2(w.c, w.d);
             }
             if (alive) {
-                sp.x[i] = x;
-                sp.vx[i] = vx;
+                st32(sp.x, i, x);
+                st32(sp.vx, i, vx);
                 double fn;
                 jn = cell_frac(P, x, fn);
                 an = frac_units(fn);
@@ -422,7 +454,7 @@ __global__ __launch_bounds__(kAdvBlock) void k_push_e(Params P, Soa sp, int64_t*
         }
         const int64_t hp = wave_append(act && !alive, &P.cnt->nh[kElectron]);
         if (hp >= 0) {
-            if (hp < P.max_holes) P.holes[kElectron][hp] = uint32_t(i);
+            if (hp < P.max_holes) P.holes[kElectron][hp] = i;
             else set_err(P, kErrLosses);
         }
         {   // candidates: one LDS atomic per wave into the block's segment
@@ -433,9 +465,9 @@ __global__ __launch_bounds__(kAdvBlock) void k_push_e(Params P, Soa sp, int64_t*
                 if (lane_id() == leader) base = atomicAdd(&ncand, __popcll((unsigned long long)m));
                 base = __shfl(base, leader);
                 if (cand) {
-                    const int q = base + int(lanes_below(m));
-                    cl[q] = uint32_t(i);
-                    cw[q] = wcd;
+                    const uint32_t q = uint32_t(base) + lanes_below(m);
+                    st32(cl, q, i);
+                    st32(cw, q, wcd);
                 }
             }
         }
