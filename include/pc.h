@@ -193,6 +193,59 @@ pc_status pc_sync(pc_handle h);
 /* Free the host-side handle (the workspace stays with the caller). */
 void pc_destroy(pc_handle h);
 
+/* ------------------------------------------------------------------ batch
+ * Many independent columns advanced together (the parameter scans of
+ * sections III and V run as one job).  Each step is one launch over the
+ * particle chunks of every column, ions on subcycle steps, and one finish
+ * workgroup per column (field, births, losses); the whole period is
+ * replayed as one HIP graph.  Columns keep their own configs, seeds, ids and
+ * buffers, and a batch column evolves bitwise exactly as the same column
+ * stepped alone with pc_step.  Columns may differ in every field except
+ * precision, ion_subcycle and sort_interval, which the batch shares. */
+typedef struct pc_batch* pc_batch_handle;
+
+typedef struct pc_tuning {
+    int32_t chunk;           /* particles per workgroup item of the particle launches */
+    int32_t sort_interval;   /* steps between counting sorts (0 = never) */
+    int32_t n_items_e, n_items_i; /* workgroups per electron / ion launch */
+    double us_per_step;      /* measured by pc_batch_tune, else 0 */
+} pc_tuning;
+
+/* Workspace bytes for n_columns configs (validates every config). */
+pc_status pc_query_batch_sizes(const pc_config* cfgs, int32_t n_columns, int64_t* workspace_bytes);
+
+/* Create and load n_columns columns in one workspace (async, as
+ * pc_init_column for each). */
+pc_status pc_init_batch(const pc_config* cfgs, int32_t n_columns, void* workspace, size_t bytes,
+                        void* hip_stream, pc_batch_handle* out);
+
+/* Advance every column by n_steps (async). */
+pc_status pc_batch_step(pc_batch_handle b, int64_t n_steps);
+
+/* Borrowed handle of column c for the per-column calls (state, counts,
+ * field, moments, deposit, solve).  pc_step, pc_set_events and the kernel
+ * timer reject it; pc_destroy ignores it (pc_batch_destroy frees it). */
+pc_status pc_batch_column(pc_batch_handle b, int32_t column, pc_handle* out);
+
+/* Autotuner: times trial_steps real steps for each chunk size in {1024,
+ * 2048, 4096, 8192} and sort interval in {10, 20, 40, 80}, keeps the fastest
+ * (blocking).  No setting changes any result. */
+pc_status pc_batch_tune(pc_batch_handle b, int32_t trial_steps, pc_tuning* out);
+pc_status pc_batch_get_tuning(pc_batch_handle b, pc_tuning* out);
+/* chunk >= 256 particles per workgroup; sort_interval >= 0 */
+pc_status pc_batch_set_tuning(pc_batch_handle b, int32_t chunk, int32_t sort_interval);
+
+/* Kernel timer of the batched electron launch (as pc_timer_enable/read). */
+pc_status pc_batch_timer_enable(pc_batch_handle b, int64_t max_launches);
+pc_status pc_batch_timer_read(pc_batch_handle b, double* total_ms, int64_t* launches);
+
+/* Synchronise and map every column's device error bits (blocking); the
+ * first failing column poisons the batch. */
+pc_status pc_batch_sync(pc_batch_handle b);
+
+/* Free the batch and its member handles (the workspace stays with the caller). */
+void pc_batch_destroy(pc_batch_handle b);
+
 const char* pc_status_string(pc_status s);
 const char* pc_last_error(void);
 

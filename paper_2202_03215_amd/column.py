@@ -52,7 +52,29 @@ class Column:
         self.h = h
         self._events = None
 
+    @classmethod
+    def _member(cls, owner: "Batch", index: int, cfg: dict) -> "Column":
+        """Borrowed view of column `index` of a batch (shares its stream)."""
+        self = cls.__new__(cls)
+        self.cfg = dict(cfg)
+        self.device = owner.device
+        self._c = N.make_config(cfg)
+        self.sizes = N.pc_sizes()
+        N.check(N.lib().pc_query_sizes(C.byref(self._c), C.byref(self.sizes)))
+        self.nn = int(self.sizes.n_nodes)
+        self.nc = int(self.sizes.n_cells)
+        self.capacity = int(self.sizes.capacity)
+        self.stream = owner.stream
+        self._owner = owner
+        h = C.c_void_p()
+        N.check(N.lib().pc_batch_column(owner.h, int(index), C.byref(h)))
+        self.h = h
+        self._events = None
+        return self
+
     def __del__(self):
+        if getattr(self, "_owner", None) is not None:
+            return   # batch members are freed with their batch
         h = getattr(self, "h", None)
         if h is not None and h.value:
             N.lib().pc_destroy(h)
@@ -174,3 +196,72 @@ class Column:
     def clear_events(self) -> None:
         N.check(N.lib().pc_set_events(self.h, None, 0, None, 0))
         self._events = None
+
+
+class Batch:
+    """Many columns advanced together by pc_init_batch / pc_batch_step in one
+    torch-owned workspace; column(c) gives a Column view of member c."""
+
+    def __init__(self, cfgs: list, device: str | torch.device = "cuda:0",
+                 stream: torch.cuda.Stream | None = None):
+        self.cfgs = [dict(c) for c in cfgs]
+        self.device = torch.device(device)
+        n = len(self.cfgs)
+        self._arr = (N.pc_config * n)(*[N.make_config(c) for c in self.cfgs])
+        nbytes = C.c_int64()
+        N.check(N.lib().pc_query_batch_sizes(self._arr, n, C.byref(nbytes)))
+        with torch.cuda.device(self.device):
+            self.stream = stream if stream is not None else torch.cuda.Stream(self.device)
+            self.workspace = torch.empty(int(nbytes.value), dtype=torch.uint8, device=self.device)
+        h = C.c_void_p()
+        self.stream.wait_stream(torch.cuda.current_stream(self.device))
+        N.check(N.lib().pc_init_batch(self._arr, n, self.workspace.data_ptr(), int(nbytes.value),
+                                      C.c_void_p(self.stream.cuda_stream), C.byref(h)))
+        self.h = h
+        self._views = {}
+
+    def __len__(self) -> int:
+        return len(self.cfgs)
+
+    def __del__(self):
+        h = getattr(self, "h", None)
+        if h is not None and h.value:
+            N.lib().pc_batch_destroy(h)
+            self.h = None
+
+    def column(self, c: int) -> Column:
+        if c not in self._views:
+            self._views[c] = Column._member(self, c, self.cfgs[c])
+        return self._views[c]
+
+    def step(self, n: int = 1) -> None:
+        self.stream.wait_stream(torch.cuda.current_stream(self.device))
+        N.check(N.lib().pc_batch_step(self.h, int(n)))
+        torch.cuda.current_stream(self.device).wait_stream(self.stream)
+
+    def sync(self) -> None:
+        N.check(N.lib().pc_batch_sync(self.h))
+
+    def tune(self, trial_steps: int = 80) -> dict:
+        t = N.pc_tuning()
+        N.check(N.lib().pc_batch_tune(self.h, int(trial_steps), C.byref(t)))
+        return dict(chunk=t.chunk, sort_interval=t.sort_interval, n_items_e=t.n_items_e,
+                    n_items_i=t.n_items_i, us_per_step=t.us_per_step)
+
+    def tuning(self) -> dict:
+        t = N.pc_tuning()
+        N.check(N.lib().pc_batch_get_tuning(self.h, C.byref(t)))
+        return dict(chunk=t.chunk, sort_interval=t.sort_interval, n_items_e=t.n_items_e,
+                    n_items_i=t.n_items_i)
+
+    def set_tuning(self, chunk: int, sort_interval: int) -> None:
+        N.check(N.lib().pc_batch_set_tuning(self.h, int(chunk), int(sort_interval)))
+
+    def timer_enable(self, max_launches: int) -> None:
+        N.check(N.lib().pc_batch_timer_enable(self.h, int(max_launches)))
+
+    def timer_read(self):
+        ms = C.c_double()
+        n = C.c_int64()
+        N.check(N.lib().pc_batch_timer_read(self.h, C.byref(ms), C.byref(n)))
+        return float(ms.value), int(n.value)

@@ -241,6 +241,7 @@ struct pc_column {
     int use_graphs;                // replay whole buffer periods as a HIP graph
     hipGraphExec_t gexec;
     int64_t gkey[6];               // bookkeeping state the graph was captured from
+    int batch_member;              // owned and stepped by a batch
 };
 
 namespace {
@@ -308,22 +309,20 @@ pc_status pc_query_sizes(const pc_config* cfg, pc_sizes* out)
     return PC_OK;
 }
 
-pc_status pc_init_column(const pc_config* cfg, void* workspace, size_t bytes, void* hip_stream, pc_handle* out)
+}  // extern "C"
+
+// Set up one column in device memory at `base` (layout(d).total bytes, 256-byte
+// aligned): particle loads, first deposit and field, leapfrog half step.
+static pc_status column_init(const pc_config* cfg, const Derived& d, char* base, hipStream_t stream,
+                             pc_column** out)
 {
-    if (!out || !workspace) return fail(PC_ERR_INVALID_ARG, "null workspace or handle");
-    *out = nullptr;
-    Derived d;
-    pc_status s = derive(cfg, &d);
-    if (s != PC_OK) return s;
+    pc_status s = PC_OK;
     const Layout L = layout(d);
-    if (int64_t(bytes) < L.total) return fail(PC_ERR_WORKSPACE, "workspace too small");
-    if (reinterpret_cast<uintptr_t>(workspace) & 255u) return fail(PC_ERR_WORKSPACE, "workspace not 256-byte aligned");
     pc_column* h = new (std::nothrow) pc_column();
     if (!h) return fail(PC_ERR_INVALID_ARG, "host allocation failed");
     h->cfg = *cfg;
     h->d = d;
-    h->st = static_cast<hipStream_t>(hip_stream);
-    char* base = static_cast<char*>(workspace);
+    h->st = stream;
     h->fp32 = d.fp32;
     for (int sp = 0; sp < 2; ++sp)
         for (int b = 0; b < 2; ++b) {
@@ -461,6 +460,22 @@ pc_status pc_init_column(const pc_config* cfg, void* workspace, size_t bytes, vo
     return PC_OK;
 }
 
+extern "C" pc_status pc_init_column(const pc_config* cfg, void* workspace, size_t bytes, void* hip_stream,
+                                    pc_handle* out)
+{
+    if (!out || !workspace) return fail(PC_ERR_INVALID_ARG, "null workspace or handle");
+    *out = nullptr;
+    Derived d;
+    pc_status s = derive(cfg, &d);
+    if (s != PC_OK) return s;
+    const Layout L = layout(d);
+    if (int64_t(bytes) < L.total) return fail(PC_ERR_WORKSPACE, "workspace too small");
+    if (reinterpret_cast<uintptr_t>(workspace) & 255u) return fail(PC_ERR_WORKSPACE, "workspace not 256-byte aligned");
+    return column_init(cfg, d, static_cast<char*>(workspace), static_cast<hipStream_t>(hip_stream), out);
+}
+
+extern "C" {
+
 // Enqueue one full time step on the column's stream and advance the host-side
 // bookkeeping (step index, charge and sort buffer parities).  With time_it,
 // the electron advance launch is bracketed by timer pair `slot`.
@@ -566,6 +581,7 @@ static pc_status capture_period(pc_column* h, int64_t period)
 pc_status pc_step(pc_handle h, int64_t n_steps)
 {
     if (!h || n_steps < 0) return fail(PC_ERR_INVALID_ARG, "bad handle or step count");
+    if (h->batch_member) return fail(PC_ERR_INVALID_ARG, "column belongs to a batch: step the batch");
     if (h->poisoned) return fail(PC_ERR_POISONED, "an earlier device error is pending");
     const int64_t period = graph_period(h);
     const bool timer_on = !h->tev.empty();
@@ -741,6 +757,7 @@ pc_status pc_set_field(pc_handle h, const double* E)
 pc_status pc_set_events(pc_handle h, uint8_t* ev_e, int64_t len_e, uint8_t* ev_i, int64_t len_i)
 {
     if (!h || len_e < 0 || len_i < 0) return fail(PC_ERR_INVALID_ARG, "bad event buffers");
+    if (h->batch_member) return fail(PC_ERR_INVALID_ARG, "batched steps record no events");
     drop_graph(h);
     h->ev[0] = ev_e;
     h->evlen[0] = ev_e ? len_e : 0;
@@ -764,6 +781,7 @@ pc_status pc_sync(pc_handle h)
 pc_status pc_timer_enable(pc_handle h, int64_t max_launches)
 {
     if (!h || max_launches < 0 || max_launches > (int64_t(1) << 24)) return fail(PC_ERR_INVALID_ARG, "bad timer size");
+    if (h->batch_member) return fail(PC_ERR_INVALID_ARG, "time the batch, not a member column");
     HIPCHK(hipStreamSynchronize(h->st));
     drop_graph(h);
     for (hipEvent_t e : h->tev) HIPCHK(hipEventDestroy(e));
@@ -795,7 +813,7 @@ pc_status pc_timer_read(pc_handle h, double* total_ms, int64_t* launches)
 
 void pc_destroy(pc_handle h)
 {
-    if (!h) return;
+    if (!h || h->batch_member) return;   // members are released with their batch
     drop_graph(h);
     for (hipEvent_t e : h->tev) (void)hipEventDestroy(e);
     delete h;
@@ -820,5 +838,446 @@ const char* pc_status_string(pc_status s)
 }
 
 const char* pc_last_error(void) { return g_last_error.c_str(); }
+
+}  // extern "C"
+
+// ===================================================================== batch
+// Many independent columns advanced together: one launch per phase covers
+// every column (particle chunks of all columns, then one finish workgroup
+// per column), so small columns share the GPU instead of each leaving most
+// of it idle.  Columns keep their own parameters, seeds, particle ids and
+// buffers; a column stepped in a batch evolves exactly as it would alone.
+
+using pcdev::BatchItem;
+using pcdev::BatchStep;
+using pcdev::ColumnDev;
+
+namespace {
+constexpr int kMinChunk = 256;   // smallest chunk (particles per workgroup) the tuner may pick
+}
+
+struct pc_batch {
+    std::vector<pc_column*> cols;
+    std::vector<int64_t> col_off;  // workspace offset of each column
+    int fp32, S, K, chunk;
+    hipStream_t st;
+    ColumnDev* dcols;
+    BatchItem* ditems[2];
+    int64_t items_cap;
+    int n_items[2];
+    int64_t step;
+    int cur[2], re_cur, ri_cur;
+    int poisoned;
+    int use_graphs;
+    hipGraphExec_t gexec;
+    int64_t gkey[7];
+    std::vector<hipEvent_t> tev;   // timer pool: 2 events per electron push launch
+    int64_t tcount;
+};
+
+namespace {
+
+struct BatchLayout {
+    int64_t cols, items[2], items_cap, total;
+    std::vector<int64_t> col_off;
+};
+
+pc_status batch_layout(const pc_config* cfgs, int32_t n, std::vector<Derived>& ds, BatchLayout& BL)
+{
+    if (!cfgs || n < 1 || n > 65535) return fail(PC_ERR_INVALID_ARG, "batch needs 1..65535 column configs");
+    ds.resize(n);
+    for (int32_t c = 0; c < n; ++c) {
+        const pc_status s = derive(&cfgs[c], &ds[c]);
+        if (s != PC_OK) return fail(s, "column " + std::to_string(c) + ": " + g_last_error);
+        if (cfgs[c].precision != cfgs[0].precision)
+            return fail(PC_ERR_INVALID_ARG, "batch columns must share one precision");
+        if (cfgs[c].ion_subcycle != cfgs[0].ion_subcycle)
+            return fail(PC_ERR_INVALID_ARG, "batch columns must share one ion subcycle");
+        if (cfgs[c].sort_interval != cfgs[0].sort_interval)
+            return fail(PC_ERR_INVALID_ARG, "batch columns must share one sort interval");
+    }
+    int64_t items = 0;
+    for (int32_t c = 0; c < n; ++c) items += (ds[c].cap + kMinChunk - 1) / kMinChunk;
+    if (items > (int64_t(1) << 31) - 1) return fail(PC_ERR_INVALID_ARG, "too many particle chunks");
+    int64_t o = 0;
+    BL.cols = o;
+    o = align256(o + int64_t(n) * int64_t(sizeof(ColumnDev)));
+    for (int s = 0; s < 2; ++s) {
+        BL.items[s] = o;
+        o = align256(o + items * int64_t(sizeof(BatchItem)));
+    }
+    BL.items_cap = items;
+    BL.col_off.resize(n);
+    for (int32_t c = 0; c < n; ++c) {
+        BL.col_off[c] = o;
+        o = align256(o + layout(ds[c]).total);
+    }
+    BL.total = o;
+    return PC_OK;
+}
+
+// item tables for one chunk size: every column's chunks, column by column
+pc_status upload_items(pc_batch* b, int chunk)
+{
+    std::vector<BatchItem> it[2];
+    for (size_t c = 0; c < b->cols.size(); ++c) {
+        const int64_t cap = b->cols[c]->d.cap;
+        const int nk = int(std::max<int64_t>(1, (cap + chunk - 1) / chunk));
+        for (int s = 0; s < 2; ++s)
+            for (int k = 0; k < nk; ++k) it[s].push_back(BatchItem{int32_t(c), k, nk, 0});
+    }
+    for (int s = 0; s < 2; ++s) {
+        if (int64_t(it[s].size()) > b->items_cap) return fail(PC_ERR_INVALID_ARG, "chunk below the minimum");
+        HIPCHK(hipMemcpyAsync(b->ditems[s], it[s].data(), it[s].size() * sizeof(BatchItem), hipMemcpyHostToDevice,
+                              b->st));
+        b->n_items[s] = int(it[s].size());
+    }
+    HIPCHK(hipStreamSynchronize(b->st));
+    b->chunk = chunk;
+    return PC_OK;
+}
+
+void batch_drop_graph(pc_batch* b)
+{
+    if (b->gexec) (void)hipGraphExecDestroy(b->gexec);
+    b->gexec = nullptr;
+}
+
+// the members' host bookkeeping follows the batch
+void batch_publish(pc_batch* b)
+{
+    for (pc_column* h : b->cols) {
+        h->step = b->step;
+        h->re_cur = b->re_cur;
+        h->ri_cur = b->ri_cur;
+        h->cur[0] = b->cur[0];
+        h->cur[1] = b->cur[1];
+        h->cfg.sort_interval = b->K;
+    }
+}
+
+pc_status enqueue_batch_step(pc_batch* b, bool time_it, int64_t slot)
+{
+    const bool ion = b->step % b->S == 0;
+    BatchStep bs{};
+    bs.cur[0] = b->cur[0];
+    bs.cur[1] = b->cur[1];
+    bs.re_new = 1 - b->re_cur;
+    bs.re_old = b->re_cur;
+    bs.ri_use = ion ? 1 - b->ri_cur : b->ri_cur;
+    bs.ri_old = ion ? b->ri_cur : -1;
+    bs.ion = ion;
+    const int n = int(b->cols.size());
+    if (time_it) HIPCHK(hipEventRecord(b->tev[2 * slot], b->st));
+    HIPCHK(pclaunch::batch_push_e(b->dcols, b->fp32, b->ditems[0], b->n_items[0], bs, b->st));
+    if (time_it) HIPCHK(hipEventRecord(b->tev[2 * slot + 1], b->st));
+    if (ion) HIPCHK(pclaunch::batch_advance_i(b->dcols, b->fp32, b->ditems[1], b->n_items[1], bs, b->st));
+    HIPCHK(pclaunch::batch_finish(b->dcols, n, b->fp32, bs, b->st));
+    b->re_cur = 1 - b->re_cur;
+    if (ion) b->ri_cur = 1 - b->ri_cur;
+    b->step += 1;
+    if (b->K > 0 && b->step % b->K == 0) {
+        for (int s = 0; s < 2; ++s) {
+            HIPCHK(pclaunch::batch_sort(b->dcols, n, b->fp32, s, b->ditems[s], b->n_items[s], b->cur[s], b->st));
+            b->cur[s] = 1 - b->cur[s];
+        }
+    }
+    return PC_OK;
+}
+
+int64_t batch_period(const pc_batch* b)
+{
+    auto lcm = [](int64_t a, int64_t c) { return a / gcd64(a, c) * c; };
+    int64_t p = lcm(2, 2 * int64_t(b->S));
+    if (b->K > 0) p = lcm(p, 2 * int64_t(b->K));
+    return p;
+}
+
+pc_status capture_batch(pc_batch* b, int64_t period)
+{
+    const int64_t step = b->step;
+    const int re = b->re_cur, ri = b->ri_cur, c0 = b->cur[0], c1 = b->cur[1];
+    batch_drop_graph(b);
+    hipError_t e = hipStreamBeginCapture(b->st, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        b->use_graphs = 0;
+        return PC_OK;
+    }
+    pc_status st = PC_OK;
+    for (int64_t k = 0; k < period && st == PC_OK; ++k) st = enqueue_batch_step(b, false, 0);
+    hipGraph_t g = nullptr;
+    e = hipStreamEndCapture(b->st, &g);
+    b->step = step;
+    b->re_cur = re;
+    b->ri_cur = ri;
+    b->cur[0] = c0;
+    b->cur[1] = c1;
+    if (st != PC_OK) {
+        if (g) (void)hipGraphDestroy(g);
+        return st;
+    }
+    if (e != hipSuccess) return hip_fail(e, "hipStreamEndCapture");
+    e = hipGraphInstantiate(&b->gexec, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (e != hipSuccess) {
+        b->gexec = nullptr;
+        return hip_fail(e, "hipGraphInstantiate");
+    }
+    const int64_t key[7] = {step % period, re, ri, c0, c1, b->K, b->chunk};
+    std::memcpy(b->gkey, key, sizeof(key));
+    return PC_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+pc_status pc_query_batch_sizes(const pc_config* cfgs, int32_t n_columns, int64_t* workspace_bytes)
+{
+    if (!workspace_bytes) return fail(PC_ERR_INVALID_ARG, "null output");
+    std::vector<Derived> ds;
+    BatchLayout BL;
+    const pc_status s = batch_layout(cfgs, n_columns, ds, BL);
+    if (s != PC_OK) return s;
+    *workspace_bytes = BL.total;
+    return PC_OK;
+}
+
+pc_status pc_init_batch(const pc_config* cfgs, int32_t n_columns, void* workspace, size_t bytes, void* hip_stream,
+                        pc_batch_handle* out)
+{
+    if (!out || !workspace) return fail(PC_ERR_INVALID_ARG, "null workspace or handle");
+    *out = nullptr;
+    std::vector<Derived> ds;
+    BatchLayout BL;
+    pc_status s = batch_layout(cfgs, n_columns, ds, BL);
+    if (s != PC_OK) return s;
+    if (int64_t(bytes) < BL.total) return fail(PC_ERR_WORKSPACE, "workspace too small");
+    if (reinterpret_cast<uintptr_t>(workspace) & 255u) return fail(PC_ERR_WORKSPACE, "workspace not 256-byte aligned");
+    pc_batch* b = new (std::nothrow) pc_batch();
+    if (!b) return fail(PC_ERR_INVALID_ARG, "host allocation failed");
+    char* base = static_cast<char*>(workspace);
+    b->st = static_cast<hipStream_t>(hip_stream);
+    b->fp32 = ds[0].fp32;
+    b->S = cfgs[0].ion_subcycle;
+    b->K = cfgs[0].sort_interval;
+    b->dcols = reinterpret_cast<ColumnDev*>(base + BL.cols);
+    b->ditems[0] = reinterpret_cast<BatchItem*>(base + BL.items[0]);
+    b->ditems[1] = reinterpret_cast<BatchItem*>(base + BL.items[1]);
+    b->items_cap = BL.items_cap;
+    b->col_off = BL.col_off;
+    b->use_graphs = 1;
+    auto cleanup = [&](pc_status st) {
+        for (pc_column* h : b->cols) {
+            h->batch_member = 0;
+            pc_destroy(h);
+        }
+        delete b;
+        return st;
+    };
+    std::vector<ColumnDev> table(n_columns);
+    for (int32_t c = 0; c < n_columns; ++c) {
+        pc_column* h = nullptr;
+        s = column_init(&cfgs[c], ds[c], base + BL.col_off[c], b->st, &h);
+        if (s != PC_OK) return cleanup(fail(s, "column " + std::to_string(c) + ": " + g_last_error));
+        h->batch_member = 1;
+        h->use_graphs = 0;
+        b->cols.push_back(h);
+        ColumnDev& C = table[c];
+        C.P = h->P;
+        for (int sp = 0; sp < 2; ++sp)
+            for (int k = 0; k < 2; ++k) {
+                C.soa[sp][k] = h->buf[sp][k];
+                C.soa32[sp][k] = h->buf32[sp][k];
+                C.rho[sp][k] = h->rho[sp][k];
+            }
+    }
+    // every column starts from the same bookkeeping state (one sort at init if K > 0)
+    b->step = 0;
+    b->re_cur = b->cols[0]->re_cur;
+    b->ri_cur = b->cols[0]->ri_cur;
+    b->cur[0] = b->cols[0]->cur[0];
+    b->cur[1] = b->cols[0]->cur[1];
+    hipError_t e = hipMemcpyAsync(b->dcols, table.data(), table.size() * sizeof(ColumnDev), hipMemcpyHostToDevice,
+                                  b->st);
+    if (e != hipSuccess) return cleanup(hip_fail(e, "pc_init_batch table"));
+    const int64_t mean_cap = [&] {
+        int64_t t = 0;
+        for (const Derived& d : ds) t += d.cap;
+        return t / n_columns;
+    }();
+    // default chunk: about four workgroups per 1024 particles of the mean column, within [1024, 4096]
+    const int chunk = int(std::min<int64_t>(4096, std::max<int64_t>(1024, mean_cap / 256)));
+    if ((s = upload_items(b, chunk)) != PC_OK) return cleanup(s);
+    batch_publish(b);
+    *out = b;
+    return PC_OK;
+}
+
+pc_status pc_batch_step(pc_batch_handle b, int64_t n_steps)
+{
+    if (!b || n_steps < 0) return fail(PC_ERR_INVALID_ARG, "bad handle or step count");
+    if (b->poisoned) return fail(PC_ERR_POISONED, "an earlier device error is pending");
+    const int64_t period = batch_period(b);
+    const bool timer_on = !b->tev.empty();
+    const int64_t tcap = int64_t(b->tev.size() / 2);
+    const bool graphs = b->use_graphs && b->st != nullptr && period <= 4096 && !timer_on;
+    int64_t left = n_steps;
+    pc_status s = PC_OK;
+    while (left > 0 && s == PC_OK) {
+        if (graphs && b->use_graphs && left >= period) {
+            const int64_t key[7] = {b->step % period, b->re_cur, b->ri_cur, b->cur[0], b->cur[1], b->K, b->chunk};
+            if (!b->gexec || std::memcmp(key, b->gkey, sizeof(key)) != 0) {
+                s = capture_batch(b, period);
+                if (s != PC_OK || !b->gexec) continue;
+            }
+            const hipError_t e = hipGraphLaunch(b->gexec, b->st);
+            if (e != hipSuccess) s = hip_fail(e, "hipGraphLaunch");
+            b->step += period;
+            left -= period;
+        } else {
+            const bool t = timer_on && b->tcount < tcap;
+            s = enqueue_batch_step(b, t, b->tcount);
+            if (t) b->tcount += 1;
+            left -= 1;
+        }
+    }
+    batch_publish(b);
+    return s;
+}
+
+pc_status pc_batch_column(pc_batch_handle b, int32_t column, pc_handle* out)
+{
+    if (!b || !out || column < 0 || column >= int32_t(b->cols.size()))
+        return fail(PC_ERR_INVALID_ARG, "bad batch column");
+    *out = b->cols[column];
+    return PC_OK;
+}
+
+pc_status pc_batch_sync(pc_batch_handle b)
+{
+    if (!b) return fail(PC_ERR_INVALID_ARG, "null handle");
+    HIPCHK(hipStreamSynchronize(b->st));
+    for (size_t c = 0; c < b->cols.size(); ++c) {
+        const pc_status s = pc_sync(b->cols[c]);
+        if (s != PC_OK) {
+            b->poisoned = 1;
+            return fail(s, "column " + std::to_string(c) + ": " + g_last_error);
+        }
+    }
+    return PC_OK;
+}
+
+pc_status pc_batch_get_tuning(pc_batch_handle b, pc_tuning* out)
+{
+    if (!b || !out) return fail(PC_ERR_INVALID_ARG, "null argument");
+    out->chunk = b->chunk;
+    out->sort_interval = b->K;
+    out->n_items_e = b->n_items[0];
+    out->n_items_i = b->n_items[1];
+    out->us_per_step = 0.0;
+    return PC_OK;
+}
+
+pc_status pc_batch_set_tuning(pc_batch_handle b, int32_t chunk, int32_t sort_interval)
+{
+    if (!b || chunk < kMinChunk || chunk > (1 << 24) || sort_interval < 0)
+        return fail(PC_ERR_INVALID_ARG, "bad tuning");
+    batch_drop_graph(b);
+    if (chunk != b->chunk) {
+        const pc_status s = upload_items(b, chunk);
+        if (s != PC_OK) return s;
+    }
+    b->K = sort_interval;
+    batch_publish(b);
+    return PC_OK;
+}
+
+// Time trial_steps real steps per (chunk, sort interval) candidate and keep
+// the fastest.  Neither setting changes any result: particle order affects
+// no draw, deposit or field value.
+pc_status pc_batch_tune(pc_batch_handle b, int32_t trial_steps, pc_tuning* out)
+{
+    if (!b || trial_steps < 1) return fail(PC_ERR_INVALID_ARG, "bad tuning arguments");
+    static const int chunks[] = {1024, 2048, 4096, 8192};
+    static const int sorts[] = {10, 20, 40, 80};
+    hipEvent_t e0, e1;
+    HIPCHK(hipEventCreate(&e0));
+    HIPCHK(hipEventCreate(&e1));
+    double best = 1e300;
+    int bc = b->chunk, bk = b->K;
+    pc_status s = PC_OK;
+    for (int ci = 0; ci < 4 && s == PC_OK; ++ci)
+        for (int ki = -1; ki < 4 && s == PC_OK; ++ki) {
+            if ((s = pc_batch_set_tuning(b, chunks[ci], sorts[ki < 0 ? 0 : ki])) != PC_OK) break;
+            hipError_t e = hipEventRecord(e0, b->st);
+            if (e == hipSuccess) s = pc_batch_step(b, trial_steps);
+            if (s == PC_OK && e == hipSuccess) e = hipEventRecord(e1, b->st);
+            if (s == PC_OK && e == hipSuccess) e = hipEventSynchronize(e1);
+            float ms = 0.0f;
+            if (s == PC_OK && e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+            if (e != hipSuccess) s = hip_fail(e, "pc_batch_tune timing");
+            if (s == PC_OK && ki >= 0 && ms < best) {   // ki < 0: warm-up of this chunk size
+                best = ms;
+                bc = chunks[ci];
+                bk = sorts[ki];
+            }
+        }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (s != PC_OK) return s;
+    if ((s = pc_batch_set_tuning(b, bc, bk)) != PC_OK) return s;
+    if ((s = pc_batch_sync(b)) != PC_OK) return s;
+    if (out) {
+        (void)pc_batch_get_tuning(b, out);
+        out->us_per_step = best * 1e3 / double(trial_steps);
+    }
+    return PC_OK;
+}
+
+pc_status pc_batch_timer_enable(pc_batch_handle b, int64_t max_launches)
+{
+    if (!b || max_launches < 0 || max_launches > (int64_t(1) << 24)) return fail(PC_ERR_INVALID_ARG, "bad timer size");
+    HIPCHK(hipStreamSynchronize(b->st));
+    batch_drop_graph(b);
+    for (hipEvent_t e : b->tev) HIPCHK(hipEventDestroy(e));
+    b->tev.clear();
+    b->tcount = 0;
+    for (int64_t k = 0; k < 2 * max_launches; ++k) {
+        hipEvent_t e;
+        HIPCHK(hipEventCreate(&e));
+        b->tev.push_back(e);
+    }
+    return PC_OK;
+}
+
+pc_status pc_batch_timer_read(pc_batch_handle b, double* total_ms, int64_t* launches)
+{
+    if (!b || !total_ms || !launches) return fail(PC_ERR_INVALID_ARG, "null argument");
+    HIPCHK(hipStreamSynchronize(b->st));
+    double tot = 0.0;
+    for (int64_t k = 0; k < b->tcount; ++k) {
+        float ms = 0.0f;
+        HIPCHK(hipEventElapsedTime(&ms, b->tev[2 * k], b->tev[2 * k + 1]));
+        tot += double(ms);
+    }
+    *total_ms = tot;
+    *launches = b->tcount;
+    b->tcount = 0;
+    return PC_OK;
+}
+
+void pc_batch_destroy(pc_batch_handle b)
+{
+    if (!b) return;
+    batch_drop_graph(b);
+    for (hipEvent_t e : b->tev) (void)hipEventDestroy(e);
+    for (pc_column* h : b->cols) {
+        h->batch_member = 0;
+        pc_destroy(h);
+    }
+    delete b;
+}
 
 }  // extern "C"

@@ -109,6 +109,32 @@ struct Params {
     int32_t* sort_off;   // counting-sort cursors, n_cells
 };
 
+// One column of a batch: its parameters and both buffers of each particle
+// store and charge array (device table read by the batched kernels).
+struct ColumnDev {
+    Params P;
+    Soa soa[2][2];       // [species][buffer], FP64 columns
+    Soa32 soa32[2][2];   // [species][buffer], FP32 columns
+    int64_t* rho[2][2];  // [species][buffer]
+};
+
+// chunk k of nk of one column's particle array
+struct BatchItem {
+    int32_t col, k, nk, pad;
+};
+
+// buffer indices of one batched step (shared by every column of the batch)
+struct BatchStep {
+    int32_t cur[2];      // particle buffer per species
+    int32_t re_new;      // electron charge buffer receiving this step's deposit
+    int32_t re_old;      // electron charge buffer cleared for the next step
+    int32_t ri_use;      // ion charge buffer used by the field (deposited on ion steps)
+    int32_t ri_old;      // ion charge buffer cleared on ion steps, else -1
+    int32_t ion;         // ions advance on this step
+    int32_t pad;
+};
+
+
 // ------------------------------------------------------------------ Philox
 // Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11): per round two 32x32->64
 // products of counter words 0 and 2 with the round multipliers, the high

@@ -119,11 +119,11 @@ __device__ __forceinline__ int64_t wave_append(bool flag, int64_t* counter)
     return flag ? int64_t(base) + int64_t(lanes_below(m)) : -1;
 }
 
-// contiguous chunk of a particle array handled by this block (64-aligned)
-__device__ __forceinline__ void block_chunk(int64_t n, int64_t& beg, int64_t& end)
+// contiguous chunk kb of nb equal (64-aligned) chunks of a particle array
+__device__ __forceinline__ void chunk_range(int64_t n, int kb, int nb, int64_t& beg, int64_t& end)
 {
-    const int64_t per = ((n + gridDim.x - 1) / gridDim.x + 63) & ~int64_t(63);
-    beg = int64_t(blockIdx.x) * per;
+    const int64_t per = ((n + nb - 1) / nb + 63) & ~int64_t(63);
+    beg = int64_t(kb) * per;
     end = beg + per < n ? beg + per : n;
 }
 
@@ -376,15 +376,15 @@ __device__ __forceinline__ void collide_one(const Params& P, const St& sp, uint8
 // collided in a second phase of the same block; collisions change only
 // velocities, so the deposit of phase 1 is final.
 template <bool EV>
-__global__ __launch_bounds__(kAdvBlock) void k_push_e(Params P, Soa sp, int64_t* __restrict__ rho,
-                                                     uint8_t* __restrict__ ev, int64_t evlen)
+__device__ __forceinline__ void push_e_chunk(const Params& P, const Soa& sp, int64_t* __restrict__ rho,
+                                             uint8_t* __restrict__ ev, int64_t evlen, int kb, int nb)
 {
     __shared__ unsigned long long win[kWindow];
     __shared__ int ncand;
     const int64_t n = P.cnt->n[kElectron];
     const uint32_t step = uint32_t(P.cnt->step);
     int64_t beg, end;
-    block_chunk(n, beg, end);
+    chunk_range(n, kb, nb, beg, end);
     if (beg >= end) return;
 
     for (int k = threadIdx.x; k < kWindow; k += kAdvBlock) win[k] = 0ull;
@@ -495,14 +495,14 @@ __global__ __launch_bounds__(kAdvBlock) void k_push_e(Params P, Soa sp, int64_t*
 // charge exchange with a Maxwellian atom (null-collision bound Ng sigma g_cap,
 // accepted with g / g_cap, the ion takes the atom's velocity), deposit.
 template <bool EV>
-__global__ __launch_bounds__(kAdvBlock) void k_advance_i(Params P, Soa sp, int64_t* __restrict__ rho,
-                                                        uint8_t* __restrict__ ev, int64_t evlen)
+__device__ __forceinline__ void advance_i_chunk(const Params& P, const Soa& sp, int64_t* __restrict__ rho,
+                                                uint8_t* __restrict__ ev, int64_t evlen, int kb, int nb)
 {
     __shared__ unsigned long long win[kWindow];
     const int64_t n = P.cnt->n[kIon];
     const uint32_t step = uint32_t(P.cnt->step);
     int64_t beg, end;
-    block_chunk(n, beg, end);
+    chunk_range(n, kb, nb, beg, end);
     if (beg >= end) return;
 
     for (int k = threadIdx.x; k < kWindow; k += kAdvBlock) win[k] = 0ull;
@@ -628,15 +628,15 @@ __device__ __forceinline__ bool push32(const Params& P, const float* __restrict_
 }
 
 template <bool EV>
-__global__ __launch_bounds__(kAdvBlock) void k_push_e32(Params P, Soa32 sp, int64_t* __restrict__ rho,
-                                                       uint8_t* __restrict__ ev, int64_t evlen)
+__device__ __forceinline__ void push_e_chunk(const Params& P, const Soa32& sp, int64_t* __restrict__ rho,
+                                             uint8_t* __restrict__ ev, int64_t evlen, int kb, int nb)
 {
     __shared__ unsigned long long win[kWindow];
     __shared__ int ncand;
     const int64_t n = P.cnt->n[kElectron];
     const uint32_t step = uint32_t(P.cnt->step);
     int64_t beg, end;
-    block_chunk(n, beg, end);
+    chunk_range(n, kb, nb, beg, end);
     if (beg >= end) return;
     for (int k = threadIdx.x; k < kWindow; k += kAdvBlock) win[k] = 0ull;
     if (threadIdx.x == 0) ncand = 0;
@@ -733,14 +733,14 @@ __global__ __launch_bounds__(kAdvBlock) void k_push_e32(Params P, Soa32 sp, int6
 }
 
 template <bool EV>
-__global__ __launch_bounds__(kAdvBlock) void k_advance_i32(Params P, Soa32 sp, int64_t* __restrict__ rho,
-                                                          uint8_t* __restrict__ ev, int64_t evlen)
+__device__ __forceinline__ void advance_i_chunk(const Params& P, const Soa32& sp, int64_t* __restrict__ rho,
+                                                uint8_t* __restrict__ ev, int64_t evlen, int kb, int nb)
 {
     __shared__ unsigned long long win[kWindow];
     const int64_t n = P.cnt->n[kIon];
     const uint32_t step = uint32_t(P.cnt->step);
     int64_t beg, end;
-    block_chunk(n, beg, end);
+    chunk_range(n, kb, nb, beg, end);
     if (beg >= end) return;
     for (int k = threadIdx.x; k < kWindow; k += kAdvBlock) win[k] = 0ull;
     const int wbase = sp.cell[beg] - kHalo;
@@ -1110,8 +1110,8 @@ __device__ __forceinline__ void deposit_global(const Params& P, const St& st, in
 }
 
 template <class St>
-__global__ __launch_bounds__(kOneBlock) void k_finish(Params P, St se, St si, int64_t* rho_e,
-                                                      int64_t* rho_i, int64_t* zero_a, int64_t* zero_b)
+__device__ __forceinline__ void finish_column(const Params& P, const St& se, const St& si, int64_t* rho_e,
+                                              int64_t* rho_i, int64_t* zero_a, int64_t* zero_b)
 {
     __shared__ int64_t sN[2], sNH[2], sID[2], sNB, sStep;
     __shared__ uint32_t sPid[kListMax];
@@ -1464,12 +1464,12 @@ __device__ __forceinline__ void count_wave(int* cw, int wbase, int32_t* glob, bo
 }
 
 template <class St>
-__global__ __launch_bounds__(256) void k_sort_count(Params P, St sp, int S)
+__device__ __forceinline__ void sort_count_chunk(const Params& P, const St& sp, int S, int kb, int nb)
 {
     __shared__ int cw[kWindow];
     const int64_t n = P.cnt->n[S];
     int64_t beg, end;
-    block_chunk(n, beg, end);
+    chunk_range(n, kb, nb, beg, end);
     if (beg >= end) return;
     for (int k = threadIdx.x; k < kWindow; k += blockDim.x) cw[k] = 0;
     const int wbase = cell_at(P, sp, beg) - kHalo;
@@ -1488,7 +1488,7 @@ __global__ __launch_bounds__(256) void k_sort_count(Params P, St sp, int S)
     }
 }
 
-__global__ __launch_bounds__(kOneBlock) void k_sort_scan(Params P)
+__device__ __forceinline__ void sort_scan_column(const Params& P)
 {
     __shared__ int64_t sh[kOneBlock / 64 + 1];
     const int nc = P.nc;
@@ -1511,13 +1511,14 @@ __global__ __launch_bounds__(kOneBlock) void k_sort_scan(Params P)
 }
 
 template <class St>
-__global__ __launch_bounds__(256) void k_sort_scatter(Params P, St src, St dst, int S)
+__device__ __forceinline__ void sort_scatter_chunk(const Params& P, const St& src, const St& dst, int S, int kb,
+                                                   int nb)
 {
     __shared__ int cw[kWindow];
     __shared__ int bw[kWindow];
     const int64_t n = P.cnt->n[S];
     int64_t beg, end;
-    block_chunk(n, beg, end);
+    chunk_range(n, kb, nb, beg, end);
     if (beg >= end) return;
     for (int k = threadIdx.x; k < kWindow; k += blockDim.x) cw[k] = 0;
     const int wbase = cell_at(P, src, beg) - kHalo;
@@ -1573,6 +1574,101 @@ __global__ __launch_bounds__(256) void k_sort_scatter(Params P, St src, St dst, 
     }
 }
 
+
+// ------------------------------------------------------- single-column kernels
+// One column per launch: block b of the grid takes chunk b.
+template <bool EV, class St>
+__global__ __launch_bounds__(kAdvBlock) void k_push_e(Params P, St sp, int64_t* __restrict__ rho,
+                                                     uint8_t* __restrict__ ev, int64_t evlen)
+{
+    push_e_chunk<EV>(P, sp, rho, ev, evlen, int(blockIdx.x), int(gridDim.x));
+}
+template <bool EV, class St>
+__global__ __launch_bounds__(kAdvBlock) void k_advance_i(Params P, St sp, int64_t* __restrict__ rho,
+                                                        uint8_t* __restrict__ ev, int64_t evlen)
+{
+    advance_i_chunk<EV>(P, sp, rho, ev, evlen, int(blockIdx.x), int(gridDim.x));
+}
+template <class St>
+__global__ __launch_bounds__(kOneBlock) void k_finish(Params P, St se, St si, int64_t* rho_e, int64_t* rho_i,
+                                                      int64_t* zero_a, int64_t* zero_b)
+{
+    finish_column(P, se, si, rho_e, rho_i, zero_a, zero_b);
+}
+template <class St>
+__global__ __launch_bounds__(256) void k_sort_count(Params P, St sp, int S)
+{
+    sort_count_chunk(P, sp, S, int(blockIdx.x), int(gridDim.x));
+}
+__global__ __launch_bounds__(kOneBlock) void k_sort_scan(Params P) { sort_scan_column(P); }
+template <class St>
+__global__ __launch_bounds__(256) void k_sort_scatter(Params P, St src, St dst, int S)
+{
+    sort_scatter_chunk(P, src, dst, S, int(blockIdx.x), int(gridDim.x));
+}
+
+// ------------------------------------------------------------ batched kernels
+// Many columns per launch.  Each column's parameters and buffers sit in a
+// device table; a launch over particle chunks takes its (column, chunk) from
+// an item table ordered by column, and the per-column single-workgroup work
+// (field, births, losses, sort scan) runs as one workgroup per column.
+template <class St> __device__ __forceinline__ const St& store_of(const ColumnDev& C, int s, int b);
+template <> __device__ __forceinline__ const Soa& store_of<Soa>(const ColumnDev& C, int s, int b)
+{
+    return C.soa[s][b];
+}
+template <> __device__ __forceinline__ const Soa32& store_of<Soa32>(const ColumnDev& C, int s, int b)
+{
+    return C.soa32[s][b];
+}
+
+template <class St>
+__global__ __launch_bounds__(kAdvBlock) void k_batch_push_e(const ColumnDev* __restrict__ cols,
+                                                           const BatchItem* __restrict__ items, BatchStep b)
+{
+    const BatchItem it = items[blockIdx.x];
+    const ColumnDev& C = cols[it.col];
+    push_e_chunk<false>(C.P, store_of<St>(C, kElectron, b.cur[kElectron]), C.rho[kElectron][b.re_new],
+                        nullptr, 0, it.k, it.nk);
+}
+template <class St>
+__global__ __launch_bounds__(kAdvBlock) void k_batch_advance_i(const ColumnDev* __restrict__ cols,
+                                                              const BatchItem* __restrict__ items, BatchStep b)
+{
+    const BatchItem it = items[blockIdx.x];
+    const ColumnDev& C = cols[it.col];
+    advance_i_chunk<false>(C.P, store_of<St>(C, kIon, b.cur[kIon]), C.rho[kIon][b.ri_use], nullptr, 0, it.k,
+                           it.nk);
+}
+template <class St>
+__global__ __launch_bounds__(kOneBlock) void k_batch_finish(const ColumnDev* __restrict__ cols, BatchStep b)
+{
+    const ColumnDev& C = cols[blockIdx.x];
+    finish_column(C.P, store_of<St>(C, kElectron, b.cur[kElectron]), store_of<St>(C, kIon, b.cur[kIon]),
+                  C.rho[kElectron][b.re_new], C.rho[kIon][b.ri_use], C.rho[kElectron][b.re_old],
+                  b.ri_old >= 0 ? C.rho[kIon][b.ri_old] : nullptr);
+}
+template <class St>
+__global__ __launch_bounds__(256) void k_batch_sort_count(const ColumnDev* __restrict__ cols,
+                                                         const BatchItem* __restrict__ items, int S, int cur)
+{
+    const BatchItem it = items[blockIdx.x];
+    const ColumnDev& C = cols[it.col];
+    sort_count_chunk(C.P, store_of<St>(C, S, cur), S, it.k, it.nk);
+}
+__global__ __launch_bounds__(kOneBlock) void k_batch_sort_scan(const ColumnDev* __restrict__ cols)
+{
+    sort_scan_column(cols[blockIdx.x].P);
+}
+template <class St>
+__global__ __launch_bounds__(256) void k_batch_sort_scatter(const ColumnDev* __restrict__ cols,
+                                                           const BatchItem* __restrict__ items, int S, int cur)
+{
+    const BatchItem it = items[blockIdx.x];
+    const ColumnDev& C = cols[it.col];
+    sort_scatter_chunk(C.P, store_of<St>(C, S, cur), store_of<St>(C, S, 1 - cur), S, it.k, it.nk);
+}
+
 }  // namespace pcdev
 
 // ------------------------------------------------------------------ launchers
@@ -1587,32 +1683,31 @@ static int grid_for(int64_t n, int block, int maxg)
     return int(g);
 }
 
-hipError_t advance(const Params& P, int species, const Soa& sp, int64_t* rho, uint8_t* ev, int64_t evlen,
-                   int grid, hipStream_t st)
+template <class St>
+static hipError_t advance_t(const Params& P, int species, const St& sp, int64_t* rho, uint8_t* ev,
+                            int64_t evlen, int grid, hipStream_t st)
 {
     const bool e = ev != nullptr;
     if (species == kElectron) {
-        if (e) hipLaunchKernelGGL(k_push_e<true>, dim3(grid), dim3(kAdvBlock), 0, st, P, sp, rho, ev, evlen);
-        else hipLaunchKernelGGL(k_push_e<false>, dim3(grid), dim3(kAdvBlock), 0, st, P, sp, rho, ev, evlen);
+        if (e) hipLaunchKernelGGL((k_push_e<true, St>), dim3(grid), dim3(kAdvBlock), 0, st, P, sp, rho, ev, evlen);
+        else hipLaunchKernelGGL((k_push_e<false, St>), dim3(grid), dim3(kAdvBlock), 0, st, P, sp, rho, ev, evlen);
     } else {
-        if (e) hipLaunchKernelGGL(k_advance_i<true>, dim3(grid), dim3(kAdvBlock), 0, st, P, sp, rho, ev, evlen);
-        else hipLaunchKernelGGL(k_advance_i<false>, dim3(grid), dim3(kAdvBlock), 0, st, P, sp, rho, ev, evlen);
+        if (e)
+            hipLaunchKernelGGL((k_advance_i<true, St>), dim3(grid), dim3(kAdvBlock), 0, st, P, sp, rho, ev, evlen);
+        else
+            hipLaunchKernelGGL((k_advance_i<false, St>), dim3(grid), dim3(kAdvBlock), 0, st, P, sp, rho, ev, evlen);
     }
     return hipGetLastError();
 }
-
+hipError_t advance(const Params& P, int species, const Soa& sp, int64_t* rho, uint8_t* ev, int64_t evlen,
+                   int grid, hipStream_t st)
+{
+    return advance_t(P, species, sp, rho, ev, evlen, grid, st);
+}
 hipError_t advance(const Params& P, int species, const Soa32& sp, int64_t* rho, uint8_t* ev, int64_t evlen,
                    int grid, hipStream_t st)
 {
-    const bool e = ev != nullptr;
-    if (species == kElectron) {
-        if (e) hipLaunchKernelGGL(k_push_e32<true>, dim3(grid), dim3(kAdvBlock), 0, st, P, sp, rho, ev, evlen);
-        else hipLaunchKernelGGL(k_push_e32<false>, dim3(grid), dim3(kAdvBlock), 0, st, P, sp, rho, ev, evlen);
-    } else {
-        if (e) hipLaunchKernelGGL(k_advance_i32<true>, dim3(grid), dim3(kAdvBlock), 0, st, P, sp, rho, ev, evlen);
-        else hipLaunchKernelGGL(k_advance_i32<false>, dim3(grid), dim3(kAdvBlock), 0, st, P, sp, rho, ev, evlen);
-    }
-    return hipGetLastError();
+    return advance_t(P, species, sp, rho, ev, evlen, grid, st);
 }
 
 template <class St>
@@ -1631,6 +1726,45 @@ hipError_t finish(const Params& P, const Soa32& se, const Soa32& si, int64_t* rh
                   int64_t* zero_a, int64_t* zero_b, hipStream_t st)
 {
     return finish_t(P, se, si, rho_e, rho_i, zero_a, zero_b, st);
+}
+
+// ---- batched launches (ColumnDev table and item tables in device memory)
+hipError_t batch_push_e(const ColumnDev* cols, int fp32, const BatchItem* items, int n, const BatchStep& b,
+                        hipStream_t st)
+{
+    if (n <= 0) return hipSuccess;
+    if (fp32) hipLaunchKernelGGL(k_batch_push_e<Soa32>, dim3(n), dim3(kAdvBlock), 0, st, cols, items, b);
+    else hipLaunchKernelGGL(k_batch_push_e<Soa>, dim3(n), dim3(kAdvBlock), 0, st, cols, items, b);
+    return hipGetLastError();
+}
+hipError_t batch_advance_i(const ColumnDev* cols, int fp32, const BatchItem* items, int n, const BatchStep& b,
+                           hipStream_t st)
+{
+    if (n <= 0) return hipSuccess;
+    if (fp32) hipLaunchKernelGGL(k_batch_advance_i<Soa32>, dim3(n), dim3(kAdvBlock), 0, st, cols, items, b);
+    else hipLaunchKernelGGL(k_batch_advance_i<Soa>, dim3(n), dim3(kAdvBlock), 0, st, cols, items, b);
+    return hipGetLastError();
+}
+hipError_t batch_finish(const ColumnDev* cols, int n_cols, int fp32, const BatchStep& b, hipStream_t st)
+{
+    if (fp32) hipLaunchKernelGGL(k_batch_finish<Soa32>, dim3(n_cols), dim3(kOneBlock), 0, st, cols, b);
+    else hipLaunchKernelGGL(k_batch_finish<Soa>, dim3(n_cols), dim3(kOneBlock), 0, st, cols, b);
+    return hipGetLastError();
+}
+template <class St>
+static hipError_t batch_sort_t(const ColumnDev* cols, int n_cols, int species, const BatchItem* items, int n,
+                               int cur, hipStream_t st)
+{
+    if (n > 0) hipLaunchKernelGGL(k_batch_sort_count<St>, dim3(n), dim3(256), 0, st, cols, items, species, cur);
+    hipLaunchKernelGGL(k_batch_sort_scan, dim3(n_cols), dim3(kOneBlock), 0, st, cols);
+    if (n > 0) hipLaunchKernelGGL(k_batch_sort_scatter<St>, dim3(n), dim3(256), 0, st, cols, items, species, cur);
+    return hipGetLastError();
+}
+hipError_t batch_sort(const ColumnDev* cols, int n_cols, int fp32, int species, const BatchItem* items, int n,
+                      int cur, hipStream_t st)
+{
+    if (fp32) return batch_sort_t<Soa32>(cols, n_cols, species, items, n, cur, st);
+    return batch_sort_t<Soa>(cols, n_cols, species, items, n, cur, st);
 }
 
 hipError_t field(const Params& P, const int64_t* rho_e, const int64_t* rho_i, double* E, double* phi,

@@ -34,6 +34,14 @@ hipError_t moments(const Params& P, const Soa32& se, const Soa32& si, int32_t cp
                    int64_t out_len, hipStream_t st);
 hipError_t sort(const Params& P, int species, const Soa& src, const Soa& dst, int grid, hipStream_t st);
 hipError_t sort(const Params& P, int species, const Soa32& src, const Soa32& dst, int grid, hipStream_t st);
+hipError_t batch_push_e(const pcdev::ColumnDev* cols, int fp32, const pcdev::BatchItem* items, int n,
+                        const pcdev::BatchStep& b, hipStream_t st);
+hipError_t batch_advance_i(const pcdev::ColumnDev* cols, int fp32, const pcdev::BatchItem* items, int n,
+                           const pcdev::BatchStep& b, hipStream_t st);
+hipError_t batch_finish(const pcdev::ColumnDev* cols, int n_cols, int fp32, const pcdev::BatchStep& b,
+                        hipStream_t st);
+hipError_t batch_sort(const pcdev::ColumnDev* cols, int n_cols, int fp32, int species, const pcdev::BatchItem* items,
+                      int n, int cur, hipStream_t st);
 int max_nodes();
 
 }  // namespace pclaunch

@@ -25,6 +25,9 @@ EXPORTS = ("pc_query_sizes", "pc_init_column", "pc_step", "pc_deposit", "pc_solv
            "pc_moments", "pc_get_counts", "pc_get_state", "pc_set_state", "pc_set_counters",
            "pc_get_field", "pc_set_field", "pc_set_events", "pc_timer_enable",
            "pc_timer_read", "pc_sync", "pc_destroy",
+           "pc_query_batch_sizes", "pc_init_batch", "pc_batch_step", "pc_batch_column",
+           "pc_batch_tune", "pc_batch_get_tuning", "pc_batch_set_tuning",
+           "pc_batch_timer_enable", "pc_batch_timer_read", "pc_batch_sync", "pc_batch_destroy",
            "pc_status_string", "pc_last_error")
 
 
@@ -57,6 +60,11 @@ class pc_counts(C.Structure):
                 ("errors", C.c_uint32), ("pad", C.c_uint32)]
 
 
+class pc_tuning(C.Structure):
+    _fields_ = [("chunk", C.c_int32), ("sort_interval", C.c_int32), ("n_items_e", C.c_int32),
+                ("n_items_i", C.c_int32), ("us_per_step", C.c_double)]
+
+
 _lib = None
 
 
@@ -87,6 +95,16 @@ def lib() -> C.CDLL:
         "pc_timer_enable": [P, I64],
         "pc_timer_read": [P, C.POINTER(C.c_double), C.POINTER(I64)],
         "pc_sync": [P],
+        "pc_query_batch_sizes": [C.POINTER(pc_config), I32, C.POINTER(I64)],
+        "pc_init_batch": [C.POINTER(pc_config), I32, P, C.c_size_t, P, C.POINTER(P)],
+        "pc_batch_step": [P, I64],
+        "pc_batch_column": [P, I32, C.POINTER(P)],
+        "pc_batch_tune": [P, I32, C.POINTER(pc_tuning)],
+        "pc_batch_get_tuning": [P, C.POINTER(pc_tuning)],
+        "pc_batch_set_tuning": [P, I32, I32],
+        "pc_batch_timer_enable": [P, I64],
+        "pc_batch_timer_read": [P, C.POINTER(C.c_double), C.POINTER(I64)],
+        "pc_batch_sync": [P],
     }
     for name, args in sig.items():
         f = getattr(L, name)
@@ -94,6 +112,8 @@ def lib() -> C.CDLL:
         f.restype = C.c_int32
     L.pc_destroy.argtypes = [P]
     L.pc_destroy.restype = None
+    L.pc_batch_destroy.argtypes = [P]
+    L.pc_batch_destroy.restype = None
     L.pc_status_string.argtypes = [C.c_int32]
     L.pc_status_string.restype = C.c_char_p
     L.pc_last_error.argtypes = []
@@ -134,3 +154,10 @@ def query_sizes(cfg: dict) -> pc_sizes:
     out = pc_sizes()
     check(lib().pc_query_sizes(C.byref(c), C.byref(out)))
     return out
+
+
+def query_batch_sizes(cfgs: list) -> int:
+    arr = (pc_config * len(cfgs))(*[make_config(c) for c in cfgs])
+    out = C.c_int64()
+    check(lib().pc_query_batch_sizes(arr, len(cfgs), C.byref(out)))
+    return int(out.value)

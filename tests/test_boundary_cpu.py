@@ -54,3 +54,20 @@ def test_bad_configs_rejected(native, bad, status):
     with pytest.raises(native.PcError) as e:
         native.query_sizes(cfg)
     assert status in str(e.value)
+
+
+def test_batch_sizes_and_rules(native):
+    a = W.tiny("periodic", seed=3)
+    b = W.tiny("bounded", n_cells=53, L=0.0053, V=5.3, seed=5)
+    one = native.query_sizes(a).workspace_bytes + native.query_sizes(b).workspace_bytes
+    both = native.query_batch_sizes([a, b])
+    assert both > one                       # columns plus the column and item tables
+    assert native.query_batch_sizes([a, b, a]) > both
+    for bad in (dict(ion_subcycle=7), dict(sort_interval=9), dict(precision="fp32")):
+        with pytest.raises(native.PcError) as e:
+            native.query_batch_sizes([a, W.with_(b, **bad)])
+        assert e.value.status == -1
+    with pytest.raises(native.PcError):
+        native.query_batch_sizes([a, W.with_(b, dt=1e-6)])   # unstable member
+    with pytest.raises(native.PcError):
+        native.query_batch_sizes([])

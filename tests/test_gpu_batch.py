@@ -1,0 +1,156 @@
+"""Batched columns (pc_init_batch / pc_batch_step) on the GPU.
+
+A column stepped inside a batch must evolve bitwise exactly as the same
+column stepped alone by pc_step (whose kernels are checked against the CPU
+oracle in the parity tests): same particles by id, same charges, same field,
+same counters.  The batch's tuning (chunk size, sort interval) and graph
+replay must not change any result, and one batch member is also checked
+step by step against the oracle from a shared state.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import workloads as W
+from tests.gpu_helpers import ELECTRON, ION, compare_states, copy_gpu_to_oracle, field_close, gpu_state
+
+pytestmark = pytest.mark.gpu
+
+QE = 1.602176634e-19
+ME = 9.1093837015e-31
+AMU = 1.66053906660e-27
+KB = 1.380649e-23
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+def _mixed(precision="fp64", sort_interval=3):
+    """Four uneven columns: periodic and bounded, neon and argon, different
+    lengths, pressures, fields, particle counts and seeds."""
+    common = dict(ion_subcycle=20, sort_interval=sort_interval, precision=precision)
+    a = W.tiny("periodic", n_cells=101, L=0.0101, V=0.0101 * 3.0e3, ppc=40, Te0_eV=8.0,
+               nu_w=5e7, seed=3, **common)
+    b = W.tiny("bounded", n_cells=64, L=0.0064, V=10.0, ppc=50, Te0_eV=6.0,
+               energy_sharing="equal", nu_w=5e7, seed=7, **common)
+    c = W.tiny("periodic", n_cells=150, L=0.015, V=0.015 * 3.0e3, ppc=30, p_torr=2.0,
+               dt=5.0e-12, seed=11, **common)
+    d = W.with_(W.tiny("periodic", n_cells=77, L=0.0077, V=0.0077 * 4.0e3, ppc=35, Te0_eV=4.0,
+                       seed=13, dt=2.0e-12, **common), **{k: v for k, v in W.ARGON.items()})
+    return [a, b, c, d]
+
+
+def _snapshot(col):
+    cnt = col.counts()
+    assert cnt["errors"] == 0
+    states = [gpu_state(col, s) for s in (ELECTRON, ION)]
+    E, re, ri = col.get_field()
+    return cnt, states, E.cpu().numpy(), re.cpu().numpy(), ri.cpu().numpy()
+
+
+def _same(a, b, what):
+    ca, sa, Ea, rea, ria = a
+    cb, sb, Eb, reb, rib = b
+    assert ca["n"] == cb["n"] and ca["next_id"] == cb["next_id"] and ca["step"] == cb["step"], what
+    for s in (ELECTRON, ION):
+        for k in range(5):
+            assert np.array_equal(sa[s][k], sb[s][k]), (what, s, k)
+    assert np.array_equal(rea, reb) and np.array_equal(ria, rib), what
+    assert np.array_equal(Ea, Eb), what
+
+
+def _batch(cfgs):
+    from paper_2202_03215_amd.column import Batch
+    return Batch(cfgs)
+
+
+def _alone(cfg, steps):
+    from paper_2202_03215_amd.column import Column
+    col = Column(cfg)
+    col.step(steps)
+    return _snapshot(col)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_batch_columns_equal_single_columns(torch_cuda, precision):
+    cfgs = _mixed(precision)
+    steps = 240                       # two graph periods of lcm(2, 40, 6) = 120 steps
+    b = _batch(cfgs)
+    b.step(steps)
+    b.sync()
+    for k, cfg in enumerate(cfgs):
+        got = _snapshot(b.column(k))
+        assert got[0]["step"] == steps
+        _same(got, _alone(cfg, steps), f"column {k}")
+    # births and losses happened in the ionizing columns
+    assert b.column(0).counts()["next_id"][0] > cfgs[0]["ppc"] * cfgs[0]["n_cells"]
+
+
+def test_batch_tuning_and_graphs_do_not_change_results(torch_cuda):
+    cfgs = _mixed("fp64", sort_interval=4)
+    steps = 200
+    ref = _batch(cfgs)
+    ref.step(steps)
+    other = _batch(cfgs)
+    other.set_tuning(256, 7)          # smallest chunks, another sort interval
+    other.step(steps // 2)
+    other.set_tuning(8192, 0)         # one chunk per column, no sort
+    other.timer_enable(steps)         # timed launches are eager
+    other.step(steps - steps // 2)
+    ms, n = other.timer_read()
+    assert n == steps - steps // 2 and ms > 0.0
+    for k in range(len(cfgs)):
+        _same(_snapshot(ref.column(k)), _snapshot(other.column(k)), f"column {k}")
+
+
+def test_batch_tuner_picks_a_setting(torch_cuda):
+    b = _batch(_mixed("fp32"))
+    t = b.tune(trial_steps=40)
+    assert t["chunk"] in (1024, 2048, 4096, 8192) and t["sort_interval"] in (10, 20, 40, 80)
+    assert t["us_per_step"] > 0.0
+    assert b.tuning()["chunk"] == t["chunk"]
+    b.sync()
+
+
+def test_batch_member_rules(torch_cuda):
+    from paper_2202_03215_amd import native as N
+    b = _batch(_mixed("fp64"))
+    col = b.column(1)
+    with pytest.raises(N.PcError):
+        col.step(1)
+    with pytest.raises(N.PcError):
+        col.set_events(16, 16)
+    with pytest.raises(N.PcError):
+        b.set_tuning(64, 3)           # chunk below the minimum
+    assert col.counts()["step"] == 0
+
+
+def test_batch_member_against_oracle(torch_cuda):
+    """Shared-state steps of one batch member against the oracle."""
+    from oracle.pco import Oracle
+    cfgs = _mixed("fp64")
+    b = _batch(cfgs)
+    k = 0
+    cfg = cfgs[k]
+    col = b.column(k)
+    orc = Oracle(cfg, init=False)
+    vth = (math.sqrt(max(cfg["Te0_eV"], 1.0) * QE / ME), math.sqrt(KB * cfg["Tg"] / (cfg["M_amu"] * AMU)))
+    for step in range(25):
+        copy_gpu_to_oracle(col, orc)
+        b.step(1)
+        orc.step(1)
+        c = col.counts()
+        assert c["errors"] == 0 and orc.errors == 0
+        assert c["n"] == (orc.count(0), orc.count(1)), step
+        assert c["next_id"] == (orc.next_id(0), orc.next_id(1)), step
+        compare_states(col, orc, cfg["L"], vth)
+        Eg, reg, rig = col.get_field()
+        Eo, reo, rio = orc.field()
+        assert np.array_equal(reg.cpu().numpy(), reo) and np.array_equal(rig.cpu().numpy(), rio), step
+        assert field_close(Eg.cpu().numpy(), Eo), step
