@@ -116,11 +116,75 @@ def measure(cfg: dict, args, tag: str) -> dict:
     return {"value": value, "elapsed": elapsed, "ne": ne_avg, "ni": ni_avg,
             "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                          "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                         "kernel": "k_push_e32" if fp32 else "k_push_e",
+                         "kernel": "k_push_e<false, Soa32>" if fp32 else "k_push_e<false, Soa>",
                          "avg_us": avg_s * 1e6, "launches": launches,
                          "bytes_per_launch": bytes_per_launch,
                          "window": "eager timed window of the same length after the graph window",
                          "ms_per_step_eager": (t3 - t2) * 1e3 / args.steps}}
+
+
+def measure_batch(cfgs: list, args) -> dict:
+    """Batched columns: autotune, warm up, then a graph-replayed timed window
+    (throughput of every column together) and an eager event-timed window of
+    the batched electron launch (roofline)."""
+    import torch
+    from paper_2202_03215_amd.column import Batch
+
+    print(f"[bench] batch: init {len(cfgs)} columns", file=sys.stderr, flush=True)
+    b = Batch(cfgs)
+    tuning = b.tune(trial_steps=40) if not args.no_tune else b.tuning()
+    print(f"[bench] batch: tuning {tuning}", file=sys.stderr, flush=True)
+    b.step(args.batch_warmup)
+    b.sync()
+
+    def totals():
+        ne = ni = 0
+        for k in range(len(cfgs)):
+            c = b.column(k).counts()
+            ne += c["n"][0]
+            ni += c["n"][1]
+        return ne, ni
+
+    S = int(cfgs[0]["ion_subcycle"])
+    step0 = b.column(0).counts()["step"]
+    ne0, ni0 = totals()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    b.step(args.batch_steps)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    b.sync()
+    ne1, ni1 = totals()
+    elapsed = t1 - t0
+    ion_steps = sum(1 for k in range(step0, step0 + args.batch_steps) if k % S == 0)
+    value = (0.5 * (ne0 + ne1) * args.batch_steps + 0.5 * (ni0 + ni1) * ion_steps) / elapsed
+    b.timer_enable(args.batch_steps)
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    b.step(args.batch_steps)
+    torch.cuda.synchronize()
+    t3 = time.perf_counter()
+    ker_ms, launches = b.timer_read()
+    b.timer_enable(0)
+    b.sync()
+    ne2, _ = totals()
+    from paper_2202_03215_amd import native as N
+    p_null = [float(N.query_sizes(c).p_null) for c in cfgs]
+    bytes_per_launch = 0.5 * (ne1 + ne2) * electron_bytes_per_step(max(p_null), True)
+    avg_s = ker_ms * 1e-3 / max(launches, 1)
+    achieved = bytes_per_launch / avg_s / 1e9
+    print(f"[bench] batch: {args.batch_steps} steps in {elapsed:.3f} s (graphs), {t3 - t2:.3f} s "
+          f"(eager); batched electron launch avg {avg_s * 1e6:.1f} us", file=sys.stderr, flush=True)
+    del b
+    torch.cuda.empty_cache()
+    return {"value": value, "ms_per_step": elapsed * 1e3 / args.batch_steps,
+            "steps": args.batch_steps, "warmup": args.batch_warmup, "electrons": int(0.5 * (ne0 + ne1)),
+            "ions": int(0.5 * (ni0 + ni1)), "tuning": tuning,
+            "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                         "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                         "kernel": "k_batch_push_e<Soa32>", "avg_us": avg_s * 1e6, "launches": launches,
+                         "bytes_per_launch": bytes_per_launch,
+                         "window": "eager timed window of the same length after the graph window"}}
 
 
 def main() -> int:
@@ -132,6 +196,11 @@ def main() -> int:
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-steps", type=int, default=0, help="oracle sample length (0 = auto)")
     ap.add_argument("--no-fp32", action="store_true", help="skip the FP32 variant")
+    ap.add_argument("--no-batch", action="store_true", help="skip the batched argon scan")
+    ap.add_argument("--no-tune", action="store_true", help="batched scan without the autotuner")
+    ap.add_argument("--batch-columns", type=int, default=64)
+    ap.add_argument("--batch-steps", type=int, default=200)
+    ap.add_argument("--batch-warmup", type=int, default=40)
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="also run a plain device copy of this many MiB (counter calibration)")
     args = ap.parse_args()
@@ -169,6 +238,13 @@ def main() -> int:
         out["fp32"] = {"value": r32["value"], "ms_per_step": r32["elapsed"] * 1e3 / args.steps,
                        "dtype": "f32 particles, f64 field", "roofline": r32["roofline"],
                        "speedup_vs_fp64": r32["value"] / value}
+    if not args.no_batch:
+        cfgs = W.argon_scan(args.batch_columns)
+        rb = measure_batch(cfgs, args)
+        out["batched"] = {"workload": f"argon_scan_{args.batch_columns}", "columns": len(cfgs),
+                          "cells": [min(c["n_cells"] for c in cfgs), max(c["n_cells"] for c in cfgs)],
+                          "dtype": "f32 particles, f64 field", **rb,
+                          "speedup_vs_plain_fp64": rb["value"] / value}
     if not args.no_cpu:
         steps = args.cpu_steps or max(5, int(4.0e8 / (ne_avg + ni_avg / S)))
         print(f"[bench] cpu baseline: oracle, {steps} steps", file=sys.stderr, flush=True)

@@ -598,7 +598,7 @@ __device__ __forceinline__ int64_t frac_units32(float off)
 __device__ __forceinline__ bool push32(const Params& P, const float* __restrict__ Ef, int& c, float& off,
                                        float& u, uint8_t& code)
 {
-    const float e0 = Ef[c], e1 = Ef[c + 1];
+    const float e0 = ld32(Ef, uint32_t(c)), e1 = ld32(Ef, uint32_t(c) + 1u);
     u = u + (e0 + off * (e1 - e0));
     off = off + u;
     const float fl = floorf(off);
@@ -644,21 +644,23 @@ __device__ __forceinline__ void push_e_chunk(const Params& P, const Soa32& sp, i
     __syncthreads();
     uint32_t* __restrict__ cl = P.cand + beg;
     uint2* __restrict__ cw = P.cand_w + beg;
+    const float* __restrict__ Ef = P.Ef_e;
     int pc = 0;
     float poff = 0.0f, pu = 0.0f;
     uint32_t pid = 0;
+    const uint32_t ue = uint32_t(end);
     {
-        const int64_t i = beg + threadIdx.x;
-        if (i < end) {
-            pc = sp.cell[i];
-            poff = sp.off[i];
-            pu = sp.vx[i];
-            pid = sp.id[i];
+        const uint32_t i = uint32_t(beg) + threadIdx.x;
+        if (i < ue) {
+            pc = ld32(sp.cell, i);
+            poff = ld32(sp.off, i);
+            pu = ld32(sp.vx, i);
+            pid = ld32(sp.id, i);
         }
     }
-    for (int64_t i0 = beg; i0 < end; i0 += kAdvBlock) {
-        const int64_t i = i0 + threadIdx.x;
-        const bool act = i < end;
+    for (uint32_t i0 = uint32_t(beg); i0 < ue; i0 += kAdvBlock) {
+        const uint32_t i = i0 + threadIdx.x;
+        const bool act = i < ue;
         bool alive = false, cand = false;
         int jn = 0;
         int64_t an = 0;
@@ -666,30 +668,32 @@ __device__ __forceinline__ void push_e_chunk(const Params& P, const Soa32& sp, i
         int c = pc;
         float off = poff, u = pu;
         const uint32_t id = pid;
-        if (i + kAdvBlock < end) {
-            pc = sp.cell[i + kAdvBlock];
-            poff = sp.off[i + kAdvBlock];
-            pu = sp.vx[i + kAdvBlock];
-            pid = sp.id[i + kAdvBlock];
+        if (i + kAdvBlock < ue) {
+            pc = ld32(sp.cell, i + kAdvBlock);
+            poff = ld32(sp.off, i + kAdvBlock);
+            pu = ld32(sp.vx, i + kAdvBlock);
+            pid = ld32(sp.id, i + kAdvBlock);
         }
         if (act) {
             uint8_t code = kEvNone;
-            alive = push32(P, P.Ef_e, c, off, u, code);
+            alive = push32(P, Ef, c, off, u, code);
             if (alive) {
-                const U4 w = philox10(id, step, 0u, kStreamElectronStep, P.key0, P.key1);
-                const uint64_t k0 = draw52(w.a, w.b);
-                if (k0 >= P.kw_e) {
+                uint32_t k0, k1;
+                loop_keys(P, k0, k1);
+                const U4 w = philox10(id, step, 0u, kStreamElectronStep, k0, k1);
+                const uint64_t k = draw52(w.a, w.b);
+                if (k >= P.kw_e) {
                     alive = false;
                     code = kEvWall;
                 } else {
-                    cand = k0 < P.kn_e;
+                    cand = k < P.kn_e;
                 }
                 wcd = make_uint2(w.c, w.d);
             }
             if (alive) {
-                sp.cell[i] = c;
-                sp.off[i] = off;
-                sp.vx[i] = u;
+                st32(sp.cell, i, c);
+                st32(sp.off, i, off);
+                st32(sp.vx, i, u);
                 jn = c;
                 an = frac_units32(off);
             }
@@ -697,7 +701,7 @@ __device__ __forceinline__ void push_e_chunk(const Params& P, const Soa32& sp, i
         }
         const int64_t hp = wave_append(act && !alive, &P.cnt->nh[kElectron]);
         if (hp >= 0) {
-            if (hp < P.max_holes) P.holes[kElectron][hp] = uint32_t(i);
+            if (hp < P.max_holes) P.holes[kElectron][hp] = i;
             else set_err(P, kErrLosses);
         }
         {
@@ -708,13 +712,13 @@ __device__ __forceinline__ void push_e_chunk(const Params& P, const Soa32& sp, i
                 if (lane_id() == leader) base = atomicAdd(&ncand, __popcll((unsigned long long)m));
                 base = __shfl(base, leader);
                 if (cand) {
-                    const int q = base + int(lanes_below(m));
-                    cl[q] = uint32_t(i);
-                    cw[q] = wcd;
+                    const uint32_t q = uint32_t(base) + lanes_below(m);
+                    st32(cl, q, i);
+                    st32(cw, q, wcd);
                 }
             }
         }
-        deposit_wave(P, win, wbase, rho, alive, jn, an);
+    deposit_wave(P, win, wbase, rho, alive, jn, an);
     }
     __syncthreads();
     for (int k = threadIdx.x; k < kWindow; k += kAdvBlock) {

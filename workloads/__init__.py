@@ -91,6 +91,29 @@ def column_50cm(seed: int = 1, ppc: int = 1000) -> dict:
                p_torr=0.5, n0=1.0e15, ppc=ppc, seed=seed)
 
 
+def argon_scan(n_columns: int = 64, seed: int = 1, precision: str = "fp32") -> list:
+    """Parameter scan of uneven argon columns for one batched job: periodic
+    columns of 5-40 cm at 50 um cells (1000-8000 cells), pressures 0.5-4 Torr
+    log-uniform, imposed fields with E/p log-uniform over 2-20 V/(cm Torr)
+    (a tenfold span of drift current at equal density), 100-400 particles per
+    cell per species, n0 = 1e15 m^-3, Te0 = 2 eV.  The time step scales as
+    1/p (2 ps at 1 Torr) so that every column has the same null-collision
+    probability per step.  Column c uses seed + c."""
+    rng = np.random.default_rng(1000 + seed)
+    cols = []
+    for c in range(n_columns):
+        cells = int(rng.integers(1000, 8001))
+        L = cells * 50.0e-6
+        p = float(np.exp(rng.uniform(np.log(0.5), np.log(4.0))))
+        e_over_p = float(np.exp(rng.uniform(np.log(2.0), np.log(20.0))))   # V/(cm Torr)
+        E0 = e_over_p * p * 100.0                                          # V/m
+        ppc = int(rng.integers(100, 401))
+        cols.append(_mk(ARGON, bc="periodic", n_cells=cells, L=L, V=E0 * L, p_torr=p,
+                        n0=1.0e15, ppc=ppc, dt=2.0e-12 / p, precision=precision,
+                        seed=seed + c))
+    return cols
+
+
 def tiny(bc: str = "periodic", seed: int = 3, **kw) -> dict:
     """Small column for oracle pins and fast parity cases (several tiles, ragged)."""
     c = _mk(NEON, bc=bc, n_cells=kw.pop("n_cells", 37), L=kw.pop("L", 0.0037),
