@@ -11,7 +11,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libpc.so")
-SOURCES = ["csrc/kernels.hip", "csrc/api.hip"]
+SOURCES = ["csrc/kernels.hip", "csrc/api.hip", "csrc/mlp.hip"]
 DEPS = SOURCES + ["csrc/device.h", "csrc/launch.h"]
 
 
@@ -45,7 +45,8 @@ def stale() -> bool:
     if not os.path.exists(LIB):
         return True
     t = os.path.getmtime(LIB)
-    deps = DEPS + [os.path.join("..", "include", "pc.h")]
+    inc = os.path.join(HERE, "..", "include")
+    deps = DEPS + [os.path.join(inc, f) for f in os.listdir(inc) if f.endswith(".h")]
     return any(os.path.getmtime(os.path.join(HERE, d)) > t for d in deps)
 
 

@@ -20,7 +20,7 @@ STATUS = {
 }
 ELECTRON, ION = 0, 1
 
-# every exported symbol of include/pc.h
+# every exported symbol of include/*.h
 EXPORTS = ("pc_query_sizes", "pc_init_column", "pc_step", "pc_deposit", "pc_solve_field",
            "pc_moments", "pc_get_counts", "pc_get_state", "pc_set_state", "pc_set_counters",
            "pc_get_field", "pc_set_field", "pc_set_events", "pc_timer_enable",
@@ -28,7 +28,9 @@ EXPORTS = ("pc_query_sizes", "pc_init_column", "pc_step", "pc_deposit", "pc_solv
            "pc_query_batch_sizes", "pc_init_batch", "pc_batch_step", "pc_batch_column",
            "pc_batch_tune", "pc_batch_get_tuning", "pc_batch_set_tuning",
            "pc_batch_timer_enable", "pc_batch_timer_read", "pc_batch_sync", "pc_batch_destroy",
-           "pc_status_string", "pc_last_error")
+           "pc_status_string", "pc_last_error",
+           "pc_mlp_query", "pc_mlp_pack", "pc_mlp_forward", "pc_mlp_grad", "pc_mlp_adam",
+           "pc_mlp_last_error")
 
 
 class PcError(RuntimeError):
