@@ -154,3 +154,38 @@ def charge_profile(n_nodes: int, seed: int, scale: int = 1 << 36):
     re = rng.integers(0, scale, size=n_nodes, dtype=np.int64)
     ri = rng.integers(0, scale, size=n_nodes, dtype=np.int64)
     return re, ri
+
+
+# ------------------------------------------------------------ fluid column
+# Transport tables of the fluid model on a uniform temperature grid, columns
+# (mu_e N, D_e N, mu_eps N, D_eps N, k_iz, L/N); see include/pc_fluid.h.
+FLUID_T_MIN, FLUID_T_STEP, FLUID_T_LEN = 0.5, 0.125, 120   # 0.5 .. 15.375 eV
+
+
+def fluid_table_flat(Ngas: float = 3.2e22, nu_w: float = 1.0e5, D_eps_ratio: float = 1.0):
+    """Temperature-independent coefficients (closed-form checks): mu_e N =
+    1e24, D_e N = 3e24, mu_eps N = 5/3 mu_e N, D_eps N = D_eps_ratio 5/3 D_e N,
+    k_iz = nu_w / Ngas, L / N = 4e-15."""
+    t = np.empty((FLUID_T_LEN, 6))
+    t[:, 0] = 1.0e24
+    t[:, 1] = 3.0e24
+    t[:, 2] = 5.0 / 3.0 * 1.0e24
+    t[:, 3] = D_eps_ratio * 5.0 / 3.0 * 3.0e24
+    t[:, 4] = nu_w / Ngas
+    t[:, 5] = 4.0e-15
+    return t
+
+
+def fluid_table_smooth():
+    """Smooth synthetic temperature dependence of the right orders of magnitude
+    for a rare gas (mobility falling and diffusion rising with T, Arrhenius
+    ionisation, D_eps below 5/3 D_e so that the chi coefficient is negative)."""
+    T = FLUID_T_MIN + FLUID_T_STEP * np.arange(FLUID_T_LEN)
+    t = np.empty((FLUID_T_LEN, 6))
+    t[:, 0] = 1.2e24 / (1.0 + 0.08 * T)
+    t[:, 1] = t[:, 0] * T * (1.0 + 0.15 * np.tanh((T - 4.0) / 2.0))
+    t[:, 2] = 5.0 / 3.0 * t[:, 0] * (1.0 - 0.05 * np.tanh((T - 5.0) / 3.0))
+    t[:, 3] = 0.9 * 5.0 / 3.0 * t[:, 1]
+    t[:, 4] = 2.0e-13 * np.exp(-18.0 / T)
+    t[:, 5] = 2.0e-14 * np.exp(-9.0 / T) + 1.0e-16 * T
+    return t
