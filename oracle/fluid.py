@@ -123,14 +123,15 @@ def faces(col: FluidColumn, n, w):
 
 def cyclic_solve(a, b, c, d):
     """Solve a_j x_{j-1} + b_j x_j + c_j x_{j+1} = d_j (indices mod N) by a
-    dense LU factorisation (numpy)."""
+    sparse LU factorisation of the assembled matrix (scipy)."""
+    import scipy.sparse as sp
+    import scipy.sparse.linalg as spla
     N = b.size
-    M = np.zeros((N, N))
     i = np.arange(N)
-    M[i, i] = b
-    M[i, (i - 1) % N] += a
-    M[i, (i + 1) % N] += c
-    return np.linalg.solve(M, d)
+    M = sp.coo_matrix((np.concatenate([b, a, c]),
+                       (np.concatenate([i, i, i]), np.concatenate([i, (i - 1) % N, (i + 1) % N]))),
+                      shape=(N, N)).tocsc()
+    return spla.spsolve(M, d)
 
 
 def step(col: FluidColumn, n, w):

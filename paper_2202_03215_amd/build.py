@@ -11,7 +11,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libpc.so")
-SOURCES = ["csrc/kernels.hip", "csrc/api.hip", "csrc/mlp.hip"]
+SOURCES = ["csrc/kernels.hip", "csrc/api.hip", "csrc/mlp.hip", "csrc/fluid.hip"]
 DEPS = SOURCES + ["csrc/device.h", "csrc/launch.h"]
 
 

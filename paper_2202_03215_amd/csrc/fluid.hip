@@ -1,0 +1,496 @@
+// fluid.hip -- gfx950 kernels of the batched quasi-neutral fluid column
+// (section IV of the paper, eqs. (3)-(17)).
+//
+// Per time step and column (many columns per launch, one workgroup each):
+//   k_fluid_faces  temperatures, transport coefficients from the table
+//                  (linear interpolation in T), face states, the total flux
+//                  Gamma_T fixed by the imposed mean field, the field of
+//                  eq. (17), the closure fluxes of eqs. (12)-(13) -- or the
+//                  normalised inputs of the closure network (the network then
+//                  runs on the matrix cores, mlp.hip)
+//   k_fluid_solve  sources (ionisation minus radial loss, Joule heating minus
+//                  collisional loss), backward-Euler diffusion of density and
+//                  of energy density as two cyclic tridiagonal systems in
+//                  FP64, solved by cyclic reduction in LDS
+// State and face arrays are FP32; the tridiagonal systems are FP64.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdint>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "../../include/pc_fluid.h"
+#include "../../include/pc_mlp.h"
+
+namespace pcfluid {
+
+constexpr int kFaceBlock = 256;
+constexpr int kSolveBlock = 1024;
+constexpr int kMaxCells = 4096;
+constexpr int kCols = 6;   // table columns
+
+struct ColDev {
+    double L, Ngas, E0, nu_w, muiN;
+};
+
+struct Globals {
+    int32_t N, K, mlp, pad;
+    float T_min, T_step, n_floor, dt;
+    const float* table;        // [K][6]
+    const ColDev* cols;
+    float *n, *w;              // [col][N]
+    float *gam, *H, *E, *Da, *kap, *dn, *dT;   // faces [col][N], face j between cells j and j+1
+    float* x;                  // closure-network inputs [col][N][5]
+    const float* y;            // closure-network outputs [col][N][2]
+    float norm[14];            // inputs (x - off) * scale (5 + 5), outputs y * scale + off (2 + 2)
+};
+
+// coefficient row at T (clamped) and its slope
+struct Coef {
+    float v[kCols];
+    float s[kCols];
+};
+
+__device__ __forceinline__ Coef interp(const Globals& G, float T)
+{
+    const float Tmax = G.T_min + float(G.K - 1) * G.T_step;
+    const float Tc = fminf(fmaxf(T, G.T_min), Tmax);
+    const float u = (Tc - G.T_min) / G.T_step;
+    int k = int(floorf(u));
+    if (k > G.K - 2) k = G.K - 2;
+    if (k < 0) k = 0;
+    const float f = u - float(k);
+    Coef c;
+    const float* lo = G.table + k * kCols;
+    const float* hi = lo + kCols;
+#pragma unroll
+    for (int q = 0; q < kCols; ++q) {
+        const float d = hi[q] - lo[q];
+        c.v[q] = lo[q] + f * d;
+        c.s[q] = d / G.T_step;
+    }
+    return c;
+}
+
+__device__ __forceinline__ double block_sum_d(double v, double* sh)
+{
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o);
+    const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+    __syncthreads();
+    if (l == 0) sh[w] = v;
+    __syncthreads();
+    double t = 0.0;
+    for (int k = 0; k < int(blockDim.x >> 6); ++k) t += sh[k];   // fixed order
+    return t;
+}
+
+// face quantities of face j (between cells j and j+1) of one column
+struct FaceQ {
+    float nf, Tf, dn, dT, A, B, mue, De, mueps, Deps, dDe, dDeps;
+};
+
+__device__ __forceinline__ FaceQ face(const Globals& G, const ColDev& C, const float* n, const float* w, int j)
+{
+    const int N = G.N;
+    const int jr = (j + 1) & (N - 1);
+    const float Ng = float(C.Ngas);
+    const float dx = float(C.L / double(N));
+    const float n0 = n[j], n1 = n[jr];
+    const float T0 = w[j] / (1.5f * n0), T1 = w[jr] / (1.5f * n1);
+    const Coef c0 = interp(G, T0), c1 = interp(G, T1);
+    const float Phi0 = n0 * (c0.v[1] / Ng) / (c0.v[0] / Ng);
+    const float Phi1 = n1 * (c1.v[1] / Ng) / (c1.v[0] / Ng);
+    FaceQ q;
+    q.nf = 0.5f * (n0 + n1);
+    q.Tf = 0.5f * (T0 + T1);
+    q.dn = (n1 - n0) / dx;
+    q.dT = (T1 - T0) / dx;
+    const Coef cf = interp(G, q.Tf);
+    q.mue = cf.v[0] / Ng;
+    q.De = cf.v[1] / Ng;
+    q.mueps = cf.v[2] / Ng;
+    q.Deps = cf.v[3] / Ng;
+    q.dDe = cf.s[1] / Ng;
+    q.dDeps = cf.s[3] / Ng;
+    const float mui = float(C.muiN) / Ng;
+    q.A = (Phi1 - Phi0) / (dx * q.nf);
+    q.B = 1.0f / (q.nf * (q.mue + mui));
+    return q;
+}
+
+__global__ __launch_bounds__(kFaceBlock) void k_fluid_faces(Globals G)
+{
+    __shared__ double sh[kFaceBlock / 64];
+    const int col = blockIdx.x;
+    const ColDev C = G.cols[col];
+    const int N = G.N;
+    const float* n = G.n + int64_t(col) * N;
+    const float* w = G.w + int64_t(col) * N;
+    double sa = 0.0, sb = 0.0;
+    for (int j = threadIdx.x; j < N; j += blockDim.x) {
+        const FaceQ q = face(G, C, n, w, j);
+        sa += double(q.A);
+        sb += double(q.B);
+    }
+    const double SA = block_sum_d(sa, sh);
+    const double SB = block_sum_d(sb, sh);
+    const float GT = float((C.E0 + SA / N) / (SB / N));
+    const float mui = float(C.muiN / C.Ngas);
+    const int64_t o = int64_t(col) * N;
+    for (int j = threadIdx.x; j < N; j += blockDim.x) {
+        const FaceQ q = face(G, C, n, w, j);
+        const float E = -q.A + GT * q.B;
+        const float Da = mui * q.De / q.mue;
+        const float beta = 1.5f * q.Tf * q.mueps;
+        const float Gc = 1.5f * q.Tf * q.Deps;
+        const float dG = 1.5f * q.Deps + 1.5f * q.Tf * q.dDeps;
+        const float kap = q.nf * (dG - beta * q.dDe / q.mue);
+        G.E[o + j] = E;
+        G.Da[o + j] = Da;
+        G.kap[o + j] = kap;
+        G.dn[o + j] = q.dn;
+        G.dT[o + j] = q.dT;
+        if (G.mlp) {
+            const float f[5] = {q.nf, 1.5f * q.Tf, E, q.dn, 1.5f * q.dT};
+            float* xo = G.x + (o + j) * 5;
+#pragma unroll
+            for (int k = 0; k < 5; ++k) xo[k] = (f[k] - G.norm[k]) * G.norm[5 + k];
+        } else {
+            const float eta = q.nf * (mui / q.mue) * q.dDe;
+            const float chi = Gc - beta * q.De / q.mue;
+            G.gam[o + j] = -Da * q.dn - eta * q.dT - q.mue / (q.mue + mui) * GT;
+            G.H[o + j] = -chi * q.dn - kap * q.dT - beta / (q.mue + mui) * GT;
+        }
+    }
+}
+
+// ---- cyclic reduction for a_j x_{j-1} + b_j x_j + c_j x_{j+1} = d_j,
+// indices mod N, N a power of two; in place in LDS, solution left in d.
+// Level s (1, 2, ..., N/2) eliminates x_{j-s}, x_{j+s} from the equations
+// j = 0 mod 2s using equations j -+ s; the last level leaves one equation in
+// x_0 alone; back substitution then recovers j = s mod 2s from j -+ s.
+__device__ void cyclic_reduce(double* a, double* b, double* c, double* d, int N)
+{
+    for (int s = 1; s < N; s <<= 1) {
+        __syncthreads();
+        for (int j = threadIdx.x * 2 * s; j < N; j += blockDim.x * 2 * s) {
+            const int jm = (j - s) & (N - 1), jp = (j + s) & (N - 1);
+            const double al = -a[j] / b[jm];
+            const double ga = -c[j] / b[jp];
+            const double na = al * a[jm];
+            const double nc = ga * c[jp];
+            const double nb = b[j] + al * c[jm] + ga * a[jp];
+            const double nd = d[j] + al * d[jm] + ga * d[jp];
+            a[j] = na;
+            b[j] = nb;
+            c[j] = nc;
+            d[j] = nd;
+        }
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) d[0] = d[0] / (a[0] + b[0] + c[0]);   // x_{-N} = x_N = x_0
+    for (int s = N >> 1; s >= 1; s >>= 1) {
+        __syncthreads();
+        for (int j = s + threadIdx.x * 2 * s; j < N; j += blockDim.x * 2 * s) {
+            const int jm = (j - s) & (N - 1), jp = (j + s) & (N - 1);
+            d[j] = (d[j] - a[j] * d[jm] - c[j] * d[jp]) / b[j];
+        }
+    }
+    __syncthreads();
+}
+
+__global__ __launch_bounds__(kSolveBlock) void k_fluid_solve(Globals G)
+{
+    __shared__ double A[kMaxCells], B[kMaxCells], Cc[kMaxCells], D[kMaxCells];
+    constexpr int kRows = kMaxCells / kSolveBlock;
+    const int col = blockIdx.x;
+    const ColDev C = G.cols[col];
+    const int N = G.N;
+    const int64_t o = int64_t(col) * N;
+    float* n = G.n + o;
+    float* w = G.w + o;
+    const double dx = C.L / double(N);
+    const double dt = double(G.dt);
+    const double r = dt / (dx * dx);
+    const float Ng = float(C.Ngas);
+    double rhs_w[kRows];
+    // density system and the energy right-hand side (explicit parts)
+#pragma unroll
+    for (int k = 0; k < kRows; ++k) {
+        const int j = threadIdx.x + k * kSolveBlock;
+        rhs_w[k] = 0.0;
+        if (j < N) {
+            const int jm = (j - 1) & (N - 1);
+            float gp, gm, hp, hm;
+            if (G.mlp) {
+                gp = G.y[(o + j) * 2] * G.norm[10] + G.norm[12];
+                gm = G.y[(o + jm) * 2] * G.norm[10] + G.norm[12];
+                hp = G.y[(o + j) * 2 + 1] * G.norm[11] + G.norm[13];
+                hm = G.y[(o + jm) * 2 + 1] * G.norm[11] + G.norm[13];
+            } else {
+                gp = G.gam[o + j];
+                gm = G.gam[o + jm];
+                hp = G.H[o + j];
+                hm = G.H[o + jm];
+            }
+            const float nj = n[j], wj = w[j];
+            const Coef cc = interp(G, wj / (1.5f * nj));
+            const float Sn = nj * (Ng * cc.v[4] - float(C.nu_w));
+            const float P = -0.5f * (gm * G.E[o + jm] + gp * G.E[o + j]);
+            const float Sw = P - nj * (Ng * cc.v[5]);
+            const double Dp = G.Da[o + j], Dm = G.Da[o + jm];
+            const double gep = double(gp) + Dp * double(G.dn[o + j]);
+            const double gem = double(gm) + Dm * double(G.dn[o + jm]);
+            A[j] = -r * Dm;
+            B[j] = 1.0 + r * (Dm + Dp);
+            Cc[j] = -r * Dp;
+            D[j] = double(nj) + dt * double(Sn) - dt / dx * (gep - gem);
+            const double Kp = G.kap[o + j], Km = G.kap[o + jm];
+            const double hep = double(hp) + Kp * double(G.dT[o + j]);
+            const double hem = double(hm) + Km * double(G.dT[o + jm]);
+            rhs_w[k] = double(wj) + dt * double(Sw) - dt / dx * (hep - hem);
+        }
+    }
+    cyclic_reduce(A, B, Cc, D, N);
+#pragma unroll
+    for (int k = 0; k < kRows; ++k) {
+        const int j = threadIdx.x + k * kSolveBlock;
+        if (j < N) n[j] = fmaxf(float(D[j]), G.n_floor);
+    }
+    __syncthreads();   // new densities visible to the whole workgroup
+    // energy-density system with T' = w' / (1.5 n')
+#pragma unroll
+    for (int k = 0; k < kRows; ++k) {
+        const int j = threadIdx.x + k * kSolveBlock;
+        if (j < N) {
+            const int jm = (j - 1) & (N - 1), jp = (j + 1) & (N - 1);
+            const double Kp = G.kap[o + j], Km = G.kap[o + jm];
+            const double mm = 1.5 * double(n[jm]), m0 = 1.5 * double(n[j]), mp = 1.5 * double(n[jp]);
+            A[j] = -r * Km / mm;
+            B[j] = 1.0 + r * (Km + Kp) / m0;
+            Cc[j] = -r * Kp / mp;
+            D[j] = rhs_w[k];
+        }
+    }
+    cyclic_reduce(A, B, Cc, D, N);
+#pragma unroll
+    for (int k = 0; k < kRows; ++k) {
+        const int j = threadIdx.x + k * kSolveBlock;
+        if (j < N) w[j] = fmaxf(float(D[j]), 1.5f * n[j] * G.T_min);
+    }
+}
+
+// stand-alone batched cyclic tridiagonal solve (device arrays [ns][N]); x -> d
+__global__ __launch_bounds__(kSolveBlock) void k_cyclic(const double* a, const double* b, const double* c,
+                                                        double* d, int N)
+{
+    __shared__ double A[kMaxCells], B[kMaxCells], Cc[kMaxCells], D[kMaxCells];
+    const int64_t o = int64_t(blockIdx.x) * N;
+    for (int j = threadIdx.x; j < N; j += blockDim.x) {
+        A[j] = a[o + j];
+        B[j] = b[o + j];
+        Cc[j] = c[o + j];
+        D[j] = d[o + j];
+    }
+    cyclic_reduce(A, B, Cc, D, N);
+    for (int j = threadIdx.x; j < N; j += blockDim.x) d[o + j] = D[j];
+}
+
+}  // namespace pcfluid
+
+// ---------------------------------------------------------------- C ABI
+using namespace pcfluid;
+
+struct pc_fluid {
+    pc_fluid_config cfg;
+    Globals G;
+    hipStream_t st;
+    const void* mlp_packed;
+};
+
+namespace {
+thread_local const char* g_fluid_err = "";
+
+pc_status ferr(pc_status s, const char* m)
+{
+    g_fluid_err = m;
+    return s;
+}
+
+struct FLayout {
+    int64_t cols, table, n, w, faces[7], x, y, total;
+};
+
+bool pow2(int v) { return v > 0 && (v & (v - 1)) == 0; }
+
+pc_status validate(const pc_fluid_config* c)
+{
+    if (!c) return ferr(PC_ERR_INVALID_ARG, "null config");
+    if (c->n_columns < 1 || c->n_columns > 65535) return ferr(PC_ERR_INVALID_ARG, "n_columns");
+    if (!pow2(c->n_cells) || c->n_cells < 64 || c->n_cells > kMaxCells)
+        return ferr(PC_ERR_INVALID_ARG, "n_cells must be a power of two in [64, 4096]");
+    if (c->table_len < 2) return ferr(PC_ERR_INVALID_ARG, "table_len");
+    if (!(c->dt > 0.0) || !(c->T_step > 0.0) || !(c->T_min > 0.0) || !(c->n_floor > 0.0))
+        return ferr(PC_ERR_INVALID_ARG, "dt, T_min, T_step and n_floor must be positive");
+    return PC_OK;
+}
+
+FLayout flayout(const pc_fluid_config* c)
+{
+    FLayout L{};
+    int64_t o = 0;
+    auto take = [&](int64_t bytes) {
+        const int64_t at = o;
+        o = (o + bytes + 255) & ~int64_t(255);
+        return at;
+    };
+    const int64_t cells = int64_t(c->n_columns) * c->n_cells;
+    L.cols = take(int64_t(c->n_columns) * sizeof(ColDev));
+    L.table = take(int64_t(c->table_len) * kCols * 4);
+    L.n = take(cells * 4);
+    L.w = take(cells * 4);
+    for (int k = 0; k < 7; ++k) L.faces[k] = take(cells * 4);
+    L.x = take(cells * 5 * 4);
+    L.y = take(cells * 2 * 4);
+    L.total = o;
+    return L;
+}
+}  // namespace
+
+extern "C" {
+
+pc_status pc_fluid_query(const pc_fluid_config* cfg, int64_t* workspace_bytes)
+{
+    const pc_status s = validate(cfg);
+    if (s != PC_OK) return s;
+    if (!workspace_bytes) return ferr(PC_ERR_INVALID_ARG, "null output");
+    *workspace_bytes = flayout(cfg).total;
+    return PC_OK;
+}
+
+pc_status pc_fluid_init(const pc_fluid_config* cfg, const pc_fluid_column* cols, const double* table,
+                        void* workspace, size_t bytes, void* hip_stream, pc_fluid_handle* out)
+{
+    pc_status s = validate(cfg);
+    if (s != PC_OK) return s;
+    if (!cols || !table || !workspace || !out) return ferr(PC_ERR_INVALID_ARG, "null argument");
+    const FLayout L = flayout(cfg);
+    if (int64_t(bytes) < L.total || (reinterpret_cast<uintptr_t>(workspace) & 255u))
+        return ferr(PC_ERR_WORKSPACE, "workspace too small or misaligned");
+    for (int c = 0; c < cfg->n_columns; ++c)
+        if (!(cols[c].L > 0.0) || !(cols[c].Ngas > 0.0) || !(cols[c].muiN > 0.0) || !(cols[c].nu_w >= 0.0))
+            return ferr(PC_ERR_INVALID_ARG, "column parameters");
+    pc_fluid* h = new (std::nothrow) pc_fluid();
+    if (!h) return ferr(PC_ERR_INVALID_ARG, "host allocation failed");
+    h->cfg = *cfg;
+    h->st = static_cast<hipStream_t>(hip_stream);
+    char* b = static_cast<char*>(workspace);
+    Globals& G = h->G;
+    G.N = cfg->n_cells;
+    G.K = cfg->table_len;
+    G.mlp = 0;
+    G.T_min = float(cfg->T_min);
+    G.T_step = float(cfg->T_step);
+    G.n_floor = float(cfg->n_floor);
+    G.dt = float(cfg->dt);
+    G.cols = reinterpret_cast<const ColDev*>(b + L.cols);
+    G.table = reinterpret_cast<const float*>(b + L.table);
+    G.n = reinterpret_cast<float*>(b + L.n);
+    G.w = reinterpret_cast<float*>(b + L.w);
+    float** fa[7] = {&G.gam, &G.H, &G.E, &G.Da, &G.kap, &G.dn, &G.dT};
+    for (int k = 0; k < 7; ++k) *fa[k] = reinterpret_cast<float*>(b + L.faces[k]);
+    G.x = reinterpret_cast<float*>(b + L.x);
+    G.y = reinterpret_cast<const float*>(b + L.y);
+    std::memset(G.norm, 0, sizeof(G.norm));
+    std::vector<ColDev> cd(cfg->n_columns);
+    for (int c = 0; c < cfg->n_columns; ++c)
+        cd[c] = ColDev{cols[c].L, cols[c].Ngas, cols[c].E0, cols[c].nu_w, cols[c].muiN};
+    std::vector<float> tf(size_t(cfg->table_len) * kCols);
+    for (size_t k = 0; k < tf.size(); ++k) tf[k] = float(table[k]);
+    hipError_t e = hipMemcpyAsync(b + L.cols, cd.data(), cd.size() * sizeof(ColDev), hipMemcpyHostToDevice, h->st);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(b + L.table, tf.data(), tf.size() * 4, hipMemcpyHostToDevice, h->st);
+    if (e == hipSuccess) e = hipStreamSynchronize(h->st);
+    if (e != hipSuccess) {
+        delete h;
+        return ferr(PC_ERR_HIP, "pc_fluid_init copies");
+    }
+    *out = h;
+    return PC_OK;
+}
+
+pc_status pc_fluid_set_state(pc_fluid_handle h, const float* n, const float* w)
+{
+    if (!h || !n || !w) return ferr(PC_ERR_INVALID_ARG, "null argument");
+    const size_t bytes = size_t(h->cfg.n_columns) * h->cfg.n_cells * 4;
+    if (hipMemcpyAsync(h->G.n, n, bytes, hipMemcpyDeviceToDevice, h->st) != hipSuccess ||
+        hipMemcpyAsync(h->G.w, w, bytes, hipMemcpyDeviceToDevice, h->st) != hipSuccess)
+        return ferr(PC_ERR_HIP, "pc_fluid_set_state");
+    return PC_OK;
+}
+
+pc_status pc_fluid_get_state(pc_fluid_handle h, float* n, float* w)
+{
+    if (!h) return ferr(PC_ERR_INVALID_ARG, "null handle");
+    const size_t bytes = size_t(h->cfg.n_columns) * h->cfg.n_cells * 4;
+    if ((n && hipMemcpyAsync(n, h->G.n, bytes, hipMemcpyDeviceToDevice, h->st) != hipSuccess) ||
+        (w && hipMemcpyAsync(w, h->G.w, bytes, hipMemcpyDeviceToDevice, h->st) != hipSuccess))
+        return ferr(PC_ERR_HIP, "pc_fluid_get_state");
+    return PC_OK;
+}
+
+pc_status pc_fluid_set_closure(pc_fluid_handle h, const void* mlp_packed, const float* norm)
+{
+    if (!h || (mlp_packed && !norm)) return ferr(PC_ERR_INVALID_ARG, "bad closure arguments");
+    h->mlp_packed = mlp_packed;
+    h->G.mlp = mlp_packed != nullptr;
+    if (norm) std::memcpy(h->G.norm, norm, sizeof(h->G.norm));
+    return PC_OK;
+}
+
+pc_status pc_fluid_step(pc_fluid_handle h, int64_t n_steps)
+{
+    if (!h || n_steps < 0) return ferr(PC_ERR_INVALID_ARG, "bad step arguments");
+    const int nc = h->cfg.n_columns;
+    const int64_t cells = int64_t(nc) * h->cfg.n_cells;
+    for (int64_t k = 0; k < n_steps; ++k) {
+        hipLaunchKernelGGL(k_fluid_faces, dim3(nc), dim3(kFaceBlock), 0, h->st, h->G);
+        if (h->G.mlp) {
+            const pc_status s = pc_mlp_forward(h->mlp_packed, h->G.x, cells, const_cast<float*>(h->G.y), nullptr,
+                                               h->st);
+            if (s != PC_OK) return s;
+        }
+        hipLaunchKernelGGL(k_fluid_solve, dim3(nc), dim3(kSolveBlock), 0, h->st, h->G);
+    }
+    return hipGetLastError() == hipSuccess ? PC_OK : ferr(PC_ERR_HIP, "pc_fluid_step launch");
+}
+
+pc_status pc_fluid_get_faces(pc_fluid_handle h, float* gamma, float* H, float* E)
+{
+    if (!h) return ferr(PC_ERR_INVALID_ARG, "null handle");
+    const size_t bytes = size_t(h->cfg.n_columns) * h->cfg.n_cells * 4;
+    if (h->G.mlp && (gamma || H)) return ferr(PC_ERR_INVALID_ARG, "network closure: fluxes are not stored");
+    if ((gamma && hipMemcpyAsync(gamma, h->G.gam, bytes, hipMemcpyDeviceToDevice, h->st) != hipSuccess) ||
+        (H && hipMemcpyAsync(H, h->G.H, bytes, hipMemcpyDeviceToDevice, h->st) != hipSuccess) ||
+        (E && hipMemcpyAsync(E, h->G.E, bytes, hipMemcpyDeviceToDevice, h->st) != hipSuccess))
+        return ferr(PC_ERR_HIP, "pc_fluid_get_faces");
+    return PC_OK;
+}
+
+pc_status pc_cyclic_tridiag(const double* a, const double* b, const double* c, double* d, int32_t n_systems,
+                            int32_t n, void* hip_stream)
+{
+    if (!a || !b || !c || !d || n_systems < 1 || !pow2(n) || n < 2 || n > kMaxCells)
+        return ferr(PC_ERR_INVALID_ARG, "bad tridiagonal arguments (n a power of two <= 4096)");
+    hipLaunchKernelGGL(k_cyclic, dim3(n_systems), dim3(kSolveBlock), 0, static_cast<hipStream_t>(hip_stream), a, b,
+                       c, d, n);
+    return hipGetLastError() == hipSuccess ? PC_OK : ferr(PC_ERR_HIP, "pc_cyclic_tridiag launch");
+}
+
+void pc_fluid_destroy(pc_fluid_handle h) { delete h; }
+
+const char* pc_fluid_last_error(void) { return g_fluid_err; }
+
+}  // extern "C"
