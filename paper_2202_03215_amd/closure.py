@@ -1,0 +1,168 @@
+"""Learned closure of the fluid model: training data from PIC-MCC moments,
+the table (drift-diffusion) closure it is compared with, normalisation and
+GPU training (section IV of the paper: the fluid equations (3)-(4) need the
+electron flux and energy flux; eqs. (7)-(8) give them in drift-diffusion
+form with coefficients from 0D Boltzmann tables).
+
+Sign convention of the samples: the fluid model's, i.e. a positive mean
+field E0 along +x (the PIC column imposes E = -E0 + E_sp, so PIC samples are
+mirrored, x -> -x: E, the gradients and both fluxes change sign).
+
+Samples per cell group and time window (moments of the GPU column, summed
+every `every` steps over `window` steps):
+  features (n [m^-3], mean energy [eV], E [V/m], dn/dx, d(mean energy)/dx)
+  targets  (Gamma_e [m^-2 s^-1], H_e [eV m^-2 s^-1])
+"""
+from __future__ import annotations
+
+import numpy as np
+import torch
+
+from . import analysis as A
+
+
+def modulated_state(cfg: dict, amp_n: float, mode: int, amp_T: float, seed: int):
+    """Seeded particles with density n0 (1 + amp_n cos(k x)) for both species
+    (quasi-neutral) and electron temperature Te0 (1 + amp_T sin(k x))."""
+    rng = np.random.default_rng(seed)
+    L = cfg["L"]
+    n_part = int(cfg["ppc"]) * int(cfg["n_cells"])
+    k = 2.0 * np.pi * mode / L
+
+    def positions(n):
+        out = np.empty(0)
+        while out.size < n:
+            x = rng.random(2 * n) * L
+            keep = rng.random(2 * n) * (1.0 + abs(amp_n)) < 1.0 + amp_n * np.cos(k * x)
+            out = np.concatenate([out, x[keep]])
+        return out[:n]
+
+    qe, me, amu, kb = 1.602176634e-19, 9.1093837015e-31, 1.66053906660e-27, 1.380649e-23
+    xe = positions(n_part)
+    Te = cfg["Te0_eV"] * (1.0 + amp_T * np.sin(k * xe))
+    ve = rng.normal(size=(3, n_part)) * np.sqrt(Te * qe / me)
+    xi = positions(n_part)
+    vi = rng.normal(size=(3, n_part)) * np.sqrt(kb * cfg["Ti0_K"] / (cfg["M_amu"] * amu))
+    ids = np.arange(n_part)
+    return (xe, ve[0], ve[1], ve[2], ids), (xi, vi[0], vi[1], vi[2], ids)
+
+
+def pic_samples(cfgs: list, steps: int, every: int, window: int, group: int, amp_n=0.3, amp_T=0.2,
+                mode=2, seed=0):
+    """Run each column on the GPU from a modulated state and return samples
+    (X [M, 5], Y [M, 2]) in the fluid sign convention, plus the column index
+    of every sample."""
+    from .column import Column
+    Xs, Ys, cols = [], [], []
+    for c, cfg in enumerate(cfgs):
+        col = Column(cfg)
+        e, i = modulated_state(cfg, amp_n, mode, amp_T, seed + c)
+        col.set_state(0, *e)
+        col.set_state(1, *i)
+        col.set_counters(0, e[0].size, i[0].size)
+        nc, L = int(cfg["n_cells"]), float(cfg["L"])
+        ng = nc // group
+        dxg = L / ng
+        wmac = cfg["n0"] / cfg["ppc"]                   # real electrons per macroparticle per cell length
+        acc = None
+        nacc = 0
+        for s in range(steps // every):
+            col.step(every)
+            mom = col.moments(1).to(torch.float64)
+            E, _, _ = col.get_field()
+            Ec = 0.5 * (E + torch.roll(E, -1))          # cell average (periodic nodes)
+            part = torch.stack([mom[0:nc], mom[nc:2 * nc], mom[2 * nc:3 * nc], mom[3 * nc:4 * nc], Ec])
+            acc = part if acc is None else acc + part
+            nacc += 1
+            if (s + 1) * every % window == 0:
+                a = acc.cpu().numpy()
+                g = a.reshape(5, ng, group).sum(axis=2)
+                cnt = g[0] / nacc
+                n = cnt * wmac / group
+                eps = g[1] / A.EPS_SCALE / np.maximum(g[0], 1)
+                gam = g[2] / A.V_SCALE / nacc * wmac / group
+                H = g[3] / 16.0 / nacc * wmac / group
+                Eg = g[4] / (nacc * group)
+                dn = (np.roll(n, -1) - np.roll(n, 1)) / (2 * dxg)
+                de = (np.roll(eps, -1) - np.roll(eps, 1)) / (2 * dxg)
+                # mirror x -> -x into the fluid convention
+                Xs.append(np.stack([n, eps, -Eg, -dn, -de], axis=1))
+                Ys.append(np.stack([-gam, -H], axis=1))
+                cols.append(np.full(ng, c))
+                acc = None
+                nacc = 0
+        col.sync()
+        del col
+    return np.concatenate(Xs), np.concatenate(Ys), np.concatenate(cols)
+
+
+def transport_table(gas_cfg: dict, EN_values, Ngas: float):
+    """Two-term tables for the fluid model and the table closure: rows sorted
+    by T_e = 2/3 mean energy (columns of include/pc_fluid.h: mu_e N, D_e N,
+    mu_eps N, D_eps N, k_iz, L/N) and the T grid."""
+    from . import boltzmann
+    t = boltzmann.table(gas_cfg, EN_values)
+    o = np.argsort(t["Te"])
+    T = t["Te"][o]
+    Lrate = t["EN"][o] * t["w"][o]                    # heating per electron per N equals the loss
+    cols = np.stack([t["muN"][o], t["DN"][o], t["mu_epsN"][o], t["D_epsN"][o], t["k_iz"][o], Lrate], axis=1)
+    return T, cols
+
+
+def resample_uniform(T, cols, T_min, T_step, K):
+    """Linear resampling of a table onto the uniform grid T_min + k T_step."""
+    Tg = T_min + T_step * np.arange(K)
+    return np.stack([np.interp(Tg, T, cols[:, q]) for q in range(cols.shape[1])], axis=1)
+
+
+def table_fluxes(X, T, cols, Ngas):
+    """Local drift-diffusion fluxes (eqs. (7)-(8), coefficients from the
+    table at T = 2/3 mean energy, eq. (9) read as beta = 3/2 T mu_eps,
+    G = 3/2 T D_eps): Gamma = -n mu_e E - d(n D_e)/dx, H = -n beta E - d(n G)/dx."""
+    n, eps, E, dn, de = X.T
+    Te = 2.0 / 3.0 * eps
+    dT = 2.0 / 3.0 * de
+    c = [np.interp(Te, T, cols[:, q]) / Ngas for q in range(4)]
+    mue, De, mueps, Deps = c
+    h = 1e-3
+    dDe = (np.interp(Te + h, T, cols[:, 1]) - np.interp(Te - h, T, cols[:, 1])) / (2 * h) / Ngas
+    G = 1.5 * Te * Deps
+    dG = (1.5 * (Te + h) * np.interp(Te + h, T, cols[:, 3]) - 1.5 * (Te - h) * np.interp(Te - h, T, cols[:, 3])) \
+        / (2 * h) / Ngas
+    beta = 1.5 * Te * mueps
+    gam = -n * mue * E - De * dn - n * dDe * dT
+    H = -n * beta * E - G * dn - n * dG * dT
+    return np.stack([gam, H], axis=1)
+
+
+def normalisation(X, Y):
+    """(v - mean) / std inputs, std * y + mean outputs: the 14 numbers of
+    include/pc_fluid.h."""
+    mx, sx = X.mean(0), X.std(0) + 1e-30
+    my, sy = Y.mean(0), Y.std(0) + 1e-30
+    return np.concatenate([mx, 1.0 / sx, sy, my]).astype(np.float32)
+
+
+def normalise(X, Y, norm):
+    xn = (X - norm[:5]) * norm[5:10]
+    yn = None if Y is None else (Y - norm[12:14]) / norm[10:12]
+    return xn.astype(np.float32), (None if yn is None else yn.astype(np.float32))
+
+
+def train(X, Y, steps=2000, lr=2e-3, batch=4096, seed=0, norm=None):
+    """Train a closure network on the GPU (the library's forward, backward
+    and Adam kernels) on normalised samples; returns (net, norm, losses)."""
+    from .mlp import ClosureNet, glorot_params
+    if norm is None:
+        norm = normalisation(X, Y)
+    xn, yn = normalise(X, Y, norm)
+    net = ClosureNet(glorot_params(seed), max_batch=max(batch, 1024))
+    losses = net.train(torch.from_numpy(xn), torch.from_numpy(yn), steps=steps, lr=lr, batch=batch, seed=seed)
+    return net, norm, losses
+
+
+def predict(net, X, norm):
+    """Fluxes (physical units) predicted by a trained network."""
+    xn, _ = normalise(X, None, norm)
+    y = net.forward(torch.from_numpy(xn)).cpu().numpy().astype(np.float64)
+    return y * norm[10:12] + norm[12:14]

@@ -136,6 +136,18 @@ class ClosureNet:
         return losses.cpu().numpy()
 
 
+def glorot_params(seed: int = 0) -> np.ndarray:
+    """Initial parameters: Glorot-uniform weights, zero biases (flat layout of
+    include/pc_mlp.h), from a seeded generator."""
+    rng = np.random.default_rng(seed)
+    parts = []
+    for fan_in, fan_out in ((5, 64), (64, 64), (64, 64), (64, 2)):
+        lim = np.sqrt(6.0 / (fan_in + fan_out))
+        parts.append(rng.uniform(-lim, lim, size=fan_in * fan_out))
+        parts.append(np.zeros(fan_out))
+    return np.concatenate(parts).astype(np.float32)
+
+
 def bf16_bits_to_float(h: torch.Tensor) -> np.ndarray:
     """BF16 bit patterns (int16 tensor) -> float64 numpy array."""
     u = h.cpu().numpy().astype(np.uint16).astype(np.uint32) << 16
