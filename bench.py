@@ -187,6 +187,60 @@ def measure_batch(cfgs: list, args) -> dict:
                          "window": "eager timed window of the same length after the graph window"}}
 
 
+def measure_fluid(args, pic_ms_per_step: float, pic_dt: float) -> dict:
+    """Batched quasi-neutral fluid columns (section IV): 256 columns of 4096
+    cells (20 cm, neon-like smooth synthetic table), timed with the table
+    closure and with the closure network (BF16 matrix cores) in the loop."""
+    import numpy as np
+    import torch
+    from paper_2202_03215_amd.fluid import FluidBatch
+    from paper_2202_03215_amd.mlp import ClosureNet, glorot_params
+
+    ncol, ncell, dt, L = args.fluid_columns, 4096, 2.0e-9, 0.20
+    table = W.fluid_table_smooth()
+    rng = np.random.default_rng(5)
+    cols = []
+    for c in range(ncol):
+        p = float(np.exp(rng.uniform(np.log(0.5), np.log(2.0))))
+        cols.append(dict(L=L, Ngas=3.22e22 * p, E0=300.0 * p * float(rng.uniform(0.9, 1.3)), nu_w=2.0e4 / p,
+                         muiN=4.0e21))
+    x = (np.arange(ncell) + 0.5) / ncell
+    n0 = np.array([1e15 * (1.0 + 0.05 * np.cos(2 * np.pi * (2 + c % 5) * x)) for c in range(ncol)])
+    w0 = 1.5 * n0 * 3.0
+    out = {}
+    for closure in ("table", "network"):
+        fb = FluidBatch(cols, ncell, dt, table, W.FLUID_T_MIN, W.FLUID_T_STEP)
+        if closure == "network":
+            th = glorot_params(3)
+            th[-(64 * 2 + 2):] *= 0.01          # small output layer: fluxes near the offsets
+            net = ClosureNet(th, max_batch=1024)
+            norm = np.array([1e15, 4.5, 300.0, 0.0, 0.0, 1e-15, 0.3, 3e-3, 1e-17, 3e-3,
+                             1e18, 1e19, -1.0e19, -5e19], dtype=np.float32)
+            fb.set_closure(net, norm)
+        fb.set_state(n0, w0)
+        fb.step(args.fluid_warmup)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        fb.step(args.fluid_steps)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        n, w = fb.get_state()
+        ok = bool(torch.isfinite(n).all() and torch.isfinite(w).all())
+        us = el * 1e6 / args.fluid_steps
+        out[closure] = {"us_per_step": us, "cell_steps_per_s": ncol * ncell / (us * 1e-6), "finite": ok}
+        print(f"[bench] fluid {closure}: {us:.1f} us per step ({ncol} x {ncell} cells)", file=sys.stderr,
+              flush=True)
+        del fb
+    # wall time per simulated microsecond of one column
+    fluid_s = out["network"]["us_per_step"] * 1e-6 / dt * 1e-6 / ncol
+    pic_s = pic_ms_per_step * 1e-3 / pic_dt * 1e-6
+    return {"workload": f"fluid_{ncol}x{ncell}", "columns": ncol, "cells": ncell, "dt": dt,
+            "dtype": "f32 state, f64 tridiagonal, bf16 network", **out,
+            "wall_s_per_simulated_us_per_column": fluid_s,
+            "pic_wall_s_per_simulated_us_per_column": pic_s,
+            "wall_time_ratio_pic_over_fluid": pic_s / fluid_s}
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -201,6 +255,10 @@ def main() -> int:
     ap.add_argument("--batch-columns", type=int, default=64)
     ap.add_argument("--batch-steps", type=int, default=200)
     ap.add_argument("--batch-warmup", type=int, default=40)
+    ap.add_argument("--no-fluid", action="store_true", help="skip the batched fluid columns")
+    ap.add_argument("--fluid-columns", type=int, default=256)
+    ap.add_argument("--fluid-steps", type=int, default=200)
+    ap.add_argument("--fluid-warmup", type=int, default=20)
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="also run a plain device copy of this many MiB (counter calibration)")
     args = ap.parse_args()
@@ -245,6 +303,8 @@ def main() -> int:
                           "cells": [min(c["n_cells"] for c in cfgs), max(c["n_cells"] for c in cfgs)],
                           "dtype": "f32 particles, f64 field", **rb,
                           "speedup_vs_plain_fp64": rb["value"] / value}
+    if not args.no_fluid:
+        out["fluid"] = measure_fluid(args, elapsed * 1e3 / args.steps, float(cfg["dt"]))
     if not args.no_cpu:
         steps = args.cpu_steps or max(5, int(4.0e8 / (ne_avg + ni_avg / S)))
         print(f"[bench] cpu baseline: oracle, {steps} steps", file=sys.stderr, flush=True)
