@@ -60,7 +60,11 @@ enum {
 };
 
 enum { PC_BOUNDED = 0, PC_PERIODIC = 1 };
-enum { PC_WALL_OFF = 0, PC_WALL_FIXED = 1 };
+/* radial sink: off; fixed frequency nu_w (eq. (2)); balanced: each particle
+ * is removed with probability (ionizations since the species' previous step)
+ * / (its count), keeping the particle number constant on average as the
+ * paper's removal of one electron-ion pair per ionization does (section II) */
+enum { PC_WALL_OFF = 0, PC_WALL_FIXED = 1, PC_WALL_BALANCED = 2 };
 enum { PC_SHARE_OPB = 0, PC_SHARE_EQUAL = 1 };
 enum { PC_ELECTRON = 0, PC_ION = 1 };
 enum { PC_FP64 = 0, PC_FP32 = 1 };
@@ -102,6 +106,8 @@ typedef struct pc_counts {
     int64_t step;            /* index of the next step */
     uint32_t errors;         /* sticky device error bits */
     uint32_t pad;
+    int64_t births_last;     /* ionizations of the previous step (balanced sink) */
+    int64_t births_since_ion; /* ionizations since the last ion step (balanced sink) */
 } pc_counts;
 
 typedef struct pc_column* pc_handle;
@@ -163,6 +169,8 @@ pc_status pc_set_state(pc_handle h, int32_t species, int64_t n, const double* x,
 
 /* Set the step index and next ids (blocking). */
 pc_status pc_set_counters(pc_handle h, int64_t step, int64_t next_e, int64_t next_i);
+/* Set the ionization tallies of the balanced sink (blocking). */
+pc_status pc_set_balance(pc_handle h, int64_t births_last, int64_t births_since_ion);
 
 /* Copy the current field E^n and the charges it was solved from (async;
  * any pointer may be null). */

@@ -76,6 +76,8 @@ struct pco_column {
     uint32_t err;
     birth_t* births;
     int64_t nb, bcap;
+    /* balanced sink: ionizations of the previous step and since the last ion step */
+    int64_t births_last, births_since_ion;
 };
 
 /* ------------------------------------------------------------------ Philox */
@@ -674,11 +676,27 @@ static void remove_dead(species_t* p, const uint8_t* dead)
     p->n = w;
 }
 
+/* Balanced radial sink (the paper keeps the particle number constant by
+ * removing an electron-ion pair for every ionization, section II): each
+ * particle of a species is removed with probability (ionizations since its
+ * previous step) / (its current count), so that as many are removed on
+ * average as were created. */
+static double survival(int64_t births, int64_t n)
+{
+    if (n <= 0) return 1.0;
+    return 1.0 - (double)births / (double)n;
+}
+
 static int one_step(pco_column* c)
 {
     const uint32_t key[2] = {(uint32_t)c->cfg.seed, (uint32_t)(c->cfg.seed >> 32)};
     species_t* e = &c->sp[PCO_ELECTRON];
     species_t* i = &c->sp[PCO_ION];
+    const int ion_step = c->step % c->cfg.ion_subcycle == 0;
+    if (c->cfg.wall_mode == PCO_WALL_BALANCED) {
+        c->T_we = survival(c->births_last, e->n);
+        if (ion_step) c->T_wi = survival(c->births_since_ion, i->n);
+    }
     memset(e->ev, 0, (size_t)e->evcap);
     memset(i->ev, 0, (size_t)i->evcap);
     c->nb = 0;
@@ -688,9 +706,10 @@ static int one_step(pco_column* c)
     int rc = electron_pass(c, dead, key);
     if (rc) { free(dead); return rc; }
     remove_dead(e, dead);
-    if (c->step % c->cfg.ion_subcycle == 0) {
+    if (ion_step) {
         ion_pass(c, dead, key);
         remove_dead(i, dead);
+        c->births_since_ion = 0;
     }
     free(dead);
     /* ionization products: ids by rank of the parent id within the step */
@@ -710,6 +729,8 @@ static int one_step(pco_column* c)
         if (c->next_id[0] > 0xFFFFFFFFll || c->next_id[1] > 0xFFFFFFFFll) c->err |= PCO_ERR_IDS;
         if (grow_events(e, c->next_id[0]) || grow_events(i, c->next_id[1])) return -3;
     }
+    c->births_last = c->nb;
+    c->births_since_ion += c->nb;
     field_update(c);
     c->step += 1;
     return 0;
@@ -777,6 +798,22 @@ int pco_set_state(pco_column* c, int s, int64_t n, const double* x, const double
     p->n = n;
     if (maxid > c->next_id[s]) c->next_id[s] = maxid;
     if (grow_events(p, c->next_id[s])) return -3;
+    return 0;
+}
+
+int pco_set_balance(pco_column* c, int64_t births_last, int64_t births_since_ion)
+{
+    if (!c || births_last < 0 || births_since_ion < 0) return -1;
+    c->births_last = births_last;
+    c->births_since_ion = births_since_ion;
+    return 0;
+}
+
+int pco_get_balance(const pco_column* c, int64_t out[2])
+{
+    if (!c || !out) return -1;
+    out[0] = c->births_last;
+    out[1] = c->births_since_ion;
     return 0;
 }
 

@@ -23,7 +23,7 @@ extern "C" {
 #endif
 
 enum { PCO_BOUNDED = 0, PCO_PERIODIC = 1 };
-enum { PCO_WALL_OFF = 0, PCO_WALL_FIXED = 1 };
+enum { PCO_WALL_OFF = 0, PCO_WALL_FIXED = 1, PCO_WALL_BALANCED = 2 };
 enum { PCO_SHARE_OPB = 0, PCO_SHARE_EQUAL = 1 };
 enum { PCO_ELECTRON = 0, PCO_ION = 1 };
 
@@ -76,6 +76,9 @@ int pco_set_state(pco_column* c, int species, int64_t n, const double* x, const 
                   const double* vy, const double* vz, const uint32_t* id);
 /* set the step index and the next ids (used to start from a shared state) */
 int pco_set_counters(pco_column* c, int64_t step, int64_t next_e, int64_t next_i);
+/* balanced sink: ionizations of the previous step and since the last ion step */
+int pco_set_balance(pco_column* c, int64_t births_last, int64_t births_since_ion);
+int pco_get_balance(const pco_column* c, int64_t out[2]);
 /* current field E^n at nodes and the charges it came from */
 int pco_get_field(const pco_column* c, double* E, int64_t* rho_e, int64_t* rho_i);
 int pco_set_field(pco_column* c, const double* E);

@@ -64,6 +64,8 @@ def lib():
         L.pco_get_state.argtypes = [P, C.c_int, d, d, d, d, u32]
         L.pco_set_state.argtypes = [P, C.c_int, C.c_int64, d, d, d, d, u32]
         L.pco_set_counters.argtypes = [P, C.c_int64, C.c_int64, C.c_int64]
+        L.pco_set_balance.argtypes = [P, C.c_int64, C.c_int64]
+        L.pco_get_balance.argtypes = [P, i64]
         L.pco_get_field.argtypes = [P, d, i64, i64]
         L.pco_set_field.argtypes = [P, d]
         L.pco_get_events.argtypes = [P, C.c_int, u8, C.c_int64]
@@ -90,7 +92,7 @@ def make_config(cfg: dict) -> pco_config:
     s.n_cells = int(cfg["n_cells"])
     s.ppc = int(cfg["ppc"])
     s.ion_subcycle = int(cfg["ion_subcycle"])
-    s.wall_mode = {"off": 0, "fixed": 1}[cfg["wall_mode"]]
+    s.wall_mode = {"off": 0, "fixed": 1, "balanced": 2}[cfg["wall_mode"]]
     s.energy_sharing = {"opb": 0, "equal": 1}[cfg["energy_sharing"]]
     s.poisson = int(cfg["poisson"])
     for k in ("L", "V", "p_torr", "Tg", "n0", "Te0_eV", "Ti0_K", "nu_w", "dt", "eps_cap",
@@ -180,6 +182,14 @@ class Oracle:
 
     def set_counters(self, step: int, next_e: int, next_i: int):
         self._chk(lib().pco_set_counters(self.h, int(step), int(next_e), int(next_i)))
+
+    def set_balance(self, births_last: int, births_since_ion: int):
+        self._chk(lib().pco_set_balance(self.h, int(births_last), int(births_since_ion)))
+
+    def balance(self):
+        out = np.zeros(2, dtype=np.int64)
+        self._chk(lib().pco_get_balance(self.h, _ptr(out, C.c_int64)))
+        return int(out[0]), int(out[1])
 
     def field(self):
         E = np.zeros(self.nn)

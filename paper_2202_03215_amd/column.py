@@ -105,7 +105,8 @@ class Column:
         c = N.pc_counts()
         N.check(N.lib().pc_get_counts(self.h, C.byref(c)))
         return dict(n=(int(c.n[0]), int(c.n[1])), next_id=(int(c.next_id[0]), int(c.next_id[1])),
-                    step=int(c.step), errors=int(c.errors))
+                    step=int(c.step), errors=int(c.errors),
+                    balance=(int(c.births_last), int(c.births_since_ion)))
 
     # ------------------------------------------------------ stand-alone ops
     def _empty(self, n, dtype):
@@ -158,6 +159,9 @@ class Column:
 
     def set_counters(self, step: int, next_e: int, next_i: int) -> None:
         N.check(N.lib().pc_set_counters(self.h, int(step), int(next_e), int(next_i)))
+
+    def set_balance(self, births_last: int, births_since_ion: int) -> None:
+        N.check(N.lib().pc_set_balance(self.h, int(births_last), int(births_since_ion)))
 
     def get_field(self):
         E = self._empty(self.nn, torch.float64)

@@ -96,7 +96,8 @@ pc_status derive(const pc_config* c, Derived* d)
     if (!(c->L > 0.0) || !(c->dt > 0.0) || c->ppc < 1 || c->ion_subcycle < 1)
         return fail(PC_ERR_INVALID_ARG, "L, dt, ppc and ion_subcycle must be positive");
     if (c->el_p != 0.5 && c->el_p != -0.5) return fail(PC_ERR_INVALID_ARG, "el_p must be +0.5 or -0.5");
-    if (c->wall_mode != PC_WALL_OFF && c->wall_mode != PC_WALL_FIXED) return fail(PC_ERR_INVALID_ARG, "wall_mode");
+    if (c->wall_mode != PC_WALL_OFF && c->wall_mode != PC_WALL_FIXED && c->wall_mode != PC_WALL_BALANCED)
+        return fail(PC_ERR_INVALID_ARG, "wall_mode");
     if (c->energy_sharing != PC_SHARE_OPB && c->energy_sharing != PC_SHARE_EQUAL)
         return fail(PC_ERR_INVALID_ARG, "energy_sharing");
     if (!(c->eps_cap > 0.0) || !(c->g_cap > 0.0) || !(c->M_amu > 0.0) || !(c->n0 > 0.0) || !(c->Tg > 0.0))
@@ -386,6 +387,7 @@ static pc_status column_init(const pc_config* cfg, const Derived& d, char* base,
     P.kw_e = thr52(d.T_we);
     P.kw_i = thr52(d.T_wi);
     P.kcx = thr52(d.P_cx);
+    P.balanced = cfg->wall_mode == PC_WALL_BALANCED;
     P.u2v_e = d.dx / cfg->dt;
     P.u2v_i = d.dx / d.dti;
     P.efs_e = (-kQe * cfg->dt * cfg->dt) / (kMe * d.dx);
@@ -652,7 +654,19 @@ pc_status pc_get_counts(pc_handle h, pc_counts* out)
     out->step = h->host_cnt.step;
     out->errors = h->host_cnt.err;
     out->pad = 0;
+    out->births_last = h->host_cnt.births_last;
+    out->births_since_ion = h->host_cnt.births_since_ion;
     return PC_OK;
+}
+
+pc_status pc_set_balance(pc_handle h, int64_t births_last, int64_t births_since_ion)
+{
+    if (!h || births_last < 0 || births_since_ion < 0) return fail(PC_ERR_INVALID_ARG, "bad ionization tallies");
+    pc_status s = read_counters(h);
+    if (s != PC_OK) return s;
+    h->host_cnt.births_last = births_last;
+    h->host_cnt.births_since_ion = births_since_ion;
+    return write_counters(h);
 }
 
 pc_status pc_get_state(pc_handle h, int32_t species, double* x, double* vx, double* vy, double* vz, uint32_t* id,

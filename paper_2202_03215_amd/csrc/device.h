@@ -42,7 +42,9 @@ struct Counters {
     uint32_t pad0;
     int64_t nb;          // ionizations recorded in the current step
     int64_t nh[2];       // losses recorded in the current step
-    int64_t pad1[7];
+    int64_t births_last;       // balanced sink: ionizations of the previous step
+    int64_t births_since_ion;  // balanced sink: ionizations since the last ion step
+    int64_t pad1[5];
 };
 
 struct Birth {           // one ionization event (64 bytes)
@@ -88,7 +90,8 @@ struct Params {
     uint32_t key0, key1;
     // integer forms of the per-step thresholds on the 52-bit draw k = r >> 12
     // (k < T is the same decision as (k + 1/2) 2^-52 < P for T = ceil(P 2^52 - 1/2))
-    uint64_t kn_e, kw_e, kw_i, kcx;
+    uint64_t kn_e, kw_e, kw_i, kcx;   // kw_*: fixed sink; the balanced sink derives them per step
+    int32_t balanced, pad_b;
     // FP32 path: velocity scales (m/s per cell/step) and field scales
     double u2v_e, u2v_i;            // dx/dt, dx/dt_i
     double efs_e, efs_i;            // q dt^2/(m dx), q dt_i^2/(M dx)
@@ -272,6 +275,26 @@ __device__ __forceinline__ int64_t frac_units(double f)
 {
     const uint32_t a = uint32_t(f * kUnitD);
     return int64_t(a > uint32_t(kUnit) ? uint32_t(kUnit) : a);
+}
+
+// Integer threshold T on the 52-bit draw k with k < T  <=>  (k + 1/2) 2^-52 < p
+// (the same double arithmetic as the host's).
+__device__ __forceinline__ uint64_t thr52(double p)
+{
+    if (!(p > 0.0)) return 0;
+    if (!(p < 1.0)) return uint64_t(1) << 52;
+    return uint64_t(ceil(p * 4503599627370496.0 - 0.5));
+}
+
+// Sink thresholds of the current step.  Balanced sink (the paper removes an
+// electron-ion pair per ionization to keep the particle number constant):
+// survival 1 - (ionizations since the species' previous step) / (its count).
+__device__ __forceinline__ uint64_t sink_threshold(const Params& P, int species)
+{
+    if (!P.balanced) return species == 0 ? P.kw_e : P.kw_i;
+    const int64_t n = P.cnt->n[species];
+    const int64_t b = species == 0 ? P.cnt->births_last : P.cnt->births_since_ion;
+    return n > 0 ? thr52(1.0 - double(b) / double(n)) : (uint64_t(1) << 52);
 }
 
 }  // namespace pcdev

@@ -383,6 +383,7 @@ __device__ __forceinline__ void push_e_chunk(const Params& P, const Soa& sp, int
     __shared__ int ncand;
     const int64_t n = P.cnt->n[kElectron];
     const uint32_t step = uint32_t(P.cnt->step);
+    const uint64_t kw = sink_threshold(P, kElectron);
     int64_t beg, end;
     chunk_range(n, kb, nb, beg, end);
     if (beg >= end) return;
@@ -435,7 +436,7 @@ __device__ __forceinline__ void push_e_chunk(const Params& P, const Soa& sp, int
                 loop_keys(P, k0, k1);
                 const U4 w = philox10(id, step, 0u, kStreamElectronStep, k0, k1);
                 const uint64_t k = draw52(w.a, w.b);
-                if (k >= P.kw_e) {
+                if (k >= kw) {
                     alive = false;
                     code = kEvWall;
                 } else {
@@ -501,6 +502,7 @@ __device__ __forceinline__ void advance_i_chunk(const Params& P, const Soa& sp, 
     __shared__ unsigned long long win[kWindow];
     const int64_t n = P.cnt->n[kIon];
     const uint32_t step = uint32_t(P.cnt->step);
+    const uint64_t kw = sink_threshold(P, kIon);
     int64_t beg, end;
     chunk_range(n, kb, nb, beg, end);
     if (beg >= end) return;
@@ -532,7 +534,7 @@ __device__ __forceinline__ void advance_i_chunk(const Params& P, const Soa& sp, 
                 const U4 w = philox10(id, step, 0u, kStreamIonStep, P.key0, P.key1);
                 const uint64_t k0 = draw52(w.a, w.b);
                 const double u1 = unif52(w.c, w.d);
-                if (k0 >= P.kw_i) {
+                if (k0 >= kw) {
                     alive = false;
                     code = kEvWall;
                 } else if (k0 < P.kcx) {
@@ -635,6 +637,7 @@ __device__ __forceinline__ void push_e_chunk(const Params& P, const Soa32& sp, i
     __shared__ int ncand;
     const int64_t n = P.cnt->n[kElectron];
     const uint32_t step = uint32_t(P.cnt->step);
+    const uint64_t kw = sink_threshold(P, kElectron);
     int64_t beg, end;
     chunk_range(n, kb, nb, beg, end);
     if (beg >= end) return;
@@ -682,7 +685,7 @@ __device__ __forceinline__ void push_e_chunk(const Params& P, const Soa32& sp, i
                 loop_keys(P, k0, k1);
                 const U4 w = philox10(id, step, 0u, kStreamElectronStep, k0, k1);
                 const uint64_t k = draw52(w.a, w.b);
-                if (k >= P.kw_e) {
+                if (k >= kw) {
                     alive = false;
                     code = kEvWall;
                 } else {
@@ -743,6 +746,7 @@ __device__ __forceinline__ void advance_i_chunk(const Params& P, const Soa32& sp
     __shared__ unsigned long long win[kWindow];
     const int64_t n = P.cnt->n[kIon];
     const uint32_t step = uint32_t(P.cnt->step);
+    const uint64_t kw = sink_threshold(P, kIon);
     int64_t beg, end;
     chunk_range(n, kb, nb, beg, end);
     if (beg >= end) return;
@@ -765,7 +769,7 @@ __device__ __forceinline__ void advance_i_chunk(const Params& P, const Soa32& sp
             if (alive) {
                 const U4 w = philox10(id, step, 0u, kStreamIonStep, P.key0, P.key1);
                 const uint64_t k0 = draw52(w.a, w.b);
-                if (k0 >= P.kw_i) {
+                if (k0 >= kw) {
                     alive = false;
                     code = kEvWall;
                 } else if (k0 < P.kcx) {
@@ -1290,6 +1294,11 @@ __device__ __forceinline__ void finish_column(const Params& P, const St& se, con
         cnt->next_id[0] = sID[0] + nb;
         cnt->next_id[1] = sID[1] + nb;
         if (sID[0] + nb > 0xFFFFFFFFll || sID[1] + nb > 0xFFFFFFFFll) set_err(P, kErrIds);
+        // ionization tallies of the balanced sink (an ion step consumed the
+        // tally since the previous one)
+        const int64_t since = (sStep % P.ion_subcycle == 0) ? 0 : cnt->births_since_ion;
+        cnt->births_since_ion = since + nb;
+        cnt->births_last = nb;
         cnt->nb = 0;
         cnt->nh[0] = 0;
         cnt->nh[1] = 0;

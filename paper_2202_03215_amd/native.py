@@ -22,7 +22,7 @@ ELECTRON, ION = 0, 1
 
 # every exported symbol of include/*.h
 EXPORTS = ("pc_query_sizes", "pc_init_column", "pc_step", "pc_deposit", "pc_solve_field",
-           "pc_moments", "pc_get_counts", "pc_get_state", "pc_set_state", "pc_set_counters",
+           "pc_moments", "pc_get_counts", "pc_get_state", "pc_set_state", "pc_set_counters", "pc_set_balance",
            "pc_get_field", "pc_set_field", "pc_set_events", "pc_timer_enable",
            "pc_timer_read", "pc_sync", "pc_destroy",
            "pc_query_batch_sizes", "pc_init_batch", "pc_batch_step", "pc_batch_column",
@@ -62,7 +62,8 @@ class pc_sizes(C.Structure):
 
 class pc_counts(C.Structure):
     _fields_ = [("n", C.c_int64 * 2), ("next_id", C.c_int64 * 2), ("step", C.c_int64),
-                ("errors", C.c_uint32), ("pad", C.c_uint32)]
+                ("errors", C.c_uint32), ("pad", C.c_uint32), ("births_last", C.c_int64),
+                ("births_since_ion", C.c_int64)]
 
 
 class pc_tuning(C.Structure):
@@ -94,6 +95,7 @@ def lib() -> C.CDLL:
         "pc_get_state": [P, I32, P, P, P, P, P, I64],
         "pc_set_state": [P, I32, I64, P, P, P, P, P],
         "pc_set_counters": [P, I64, I64, I64],
+        "pc_set_balance": [P, I64, I64],
         "pc_get_field": [P, P, P, P],
         "pc_set_field": [P, P],
         "pc_set_events": [P, P, I64, P, I64],
@@ -139,7 +141,7 @@ def make_config(cfg: dict) -> pc_config:
     s.n_cells = int(cfg["n_cells"])
     s.ppc = int(cfg["ppc"])
     s.ion_subcycle = int(cfg["ion_subcycle"])
-    s.wall_mode = {"off": 0, "fixed": 1}[cfg["wall_mode"]]
+    s.wall_mode = {"off": 0, "fixed": 1, "balanced": 2}[cfg["wall_mode"]]
     s.energy_sharing = {"opb": 0, "equal": 1}[cfg["energy_sharing"]]
     s.poisson = int(cfg["poisson"])
     s.sort_interval = int(cfg.get("sort_interval", 0))

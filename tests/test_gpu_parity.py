@@ -175,6 +175,15 @@ def test_step_parity_equal_sharing_and_ions(torch_cuda):
     _run_shared_state(torch_cuda, cfg, steps=30, min_events={3: 3, 5: 3})
 
 
+def test_step_parity_balanced_sink(torch_cuda):
+    # removal probability from the previous step's ionizations (electrons) and
+    # from those since the last ion step (ions, subcycle 3)
+    cfg = W.tiny("periodic", n_cells=101, L=0.0101, V=0.0101 * 6.0e3, ppc=40, Te0_eV=8.0,
+                 wall_mode="balanced", ion_subcycle=3, sort_interval=4)
+    tot = _run_shared_state(torch_cuda, cfg, steps=40, min_events={3: 20, 4: 20})
+    assert tot[4] > 0
+
+
 def test_step_parity_long_loss_and_birth_lists(torch_cuda):
     # more than 2048 losses and ionizations in one step: the finish kernel
     # takes its global-scratch paths instead of the LDS lists

@@ -320,3 +320,31 @@ def test_constant_frequency_swarm_balance():
     assert o.errors == 0
     assert abs(np.mean(ws) / w - 1) < 0.025
     assert abs(np.mean(es) / eps_J - 1) < 0.025
+
+
+def test_balanced_sink_keeps_the_particle_number():
+    """Balanced sink: a particle is removed with probability (ionizations
+    since its species' previous step) / (count), so removals match births on
+    average (the paper's constant particle number).  Over 400 steps of an
+    ionizing column the counts stay within a few standard deviations of
+    sqrt(total births) of the start, while the fixed sink lets them grow."""
+    import workloads as W
+    from oracle.pco import Oracle
+    base = dict(n_cells=101, L=0.0101, V=0.0101 * 6.0e3, ppc=40, Te0_eV=8.0, ion_subcycle=4)
+    o = Oracle(W.tiny("periodic", wall_mode="balanced", **base))
+    n0 = (o.count(0), o.count(1))
+    births = 0
+    for _ in range(400):
+        b0 = o.next_id(0)
+        o.step(1)
+        births += o.next_id(0) - b0
+        bl, bs = o.balance()
+        assert bl == o.next_id(0) - b0            # tally of the step just taken
+    assert o.errors == 0 and births > 500
+    tol = 5.0 * births ** 0.5
+    assert abs(o.count(0) - n0[0]) <= tol, (o.count(0), n0, births)
+    assert abs(o.count(1) - n0[1]) <= tol + births / 100, (o.count(1), n0, births)
+    f = Oracle(W.tiny("periodic", wall_mode="fixed", nu_w=1e5, **base))
+    for _ in range(400):
+        f.step(1)
+    assert f.count(0) - n0[0] > 0.5 * births

@@ -24,7 +24,9 @@ Config keys (all SI unless noted):
   n0            initial plasma density [m^-3]
   ppc           macroparticles per cell per species at t=0
   Te0_eV, Ti0_K initial electron temperature [eV] and ion temperature [K]
-  wall_mode     "off" | "fixed": radial-loss sink with frequency nu_w [s^-1]
+  wall_mode     "off" | "fixed": radial-loss sink with frequency nu_w [s^-1] |
+                "balanced": removal probability = ionizations since the species'
+                previous step / its count (constant particle number on average)
   dt            electron time step [s]; ions advance every ion_subcycle steps
   eps_cap       energy [eV] up to which the null-collision bound is taken
   g_cap         relative-speed bound [m/s] of the ion null-collision method
