@@ -23,8 +23,15 @@ __device__ __forceinline__ uint32_t lanes_below(uint64_t m)
     return __builtin_amdgcn_mbcnt_hi(uint32_t(m >> 32), __builtin_amdgcn_mbcnt_lo(uint32_t(m), 0u));
 }
 
-// DPP wavefront reduction from the device library (all lanes participate)
+// DPP wavefront reductions and inclusive scans from the device library (all
+// lanes participate; fixed combination order, hence deterministic)
 extern "C" __device__ uint64_t __ockl_wfred_add_u64(uint64_t);
+extern "C" __device__ double __ockl_wfred_add_f64(double);
+extern "C" __device__ long __ockl_wfscan_add_i64(long, bool);
+extern "C" __device__ double __ockl_wfscan_add_f64(double, bool);
+
+__device__ __forceinline__ int64_t wave_incl_scan(int64_t v) { return __ockl_wfscan_add_i64(long(v), true); }
+__device__ __forceinline__ double wave_incl_scan(double v) { return __ockl_wfscan_add_f64(v, true); }
 
 __device__ __forceinline__ void set_err(const Params& P, uint32_t bits) { atomicOr(&P.cnt->err, bits); }
 
@@ -913,28 +920,22 @@ __global__ __launch_bounds__(256) void k_scale_field(Params P)
 }
 
 // ----------------------------------------------------------- block helpers
+// Exclusive scan over the block (<= 1024 threads) and the block total: DPP
+// wave scans, then wave 0 scans the (<= 16) wave totals.
 template <typename T>
 __device__ T block_excl_scan(T v, T* sh /* >= 1024/64 + 1 entries */, T& total)
 {
     const int lane = lane_id();
     const int wid = threadIdx.x >> 6;
     const int nw = blockDim.x >> 6;
-    T incl = v;
-#pragma unroll
-    for (int o = 1; o < 64; o <<= 1) {
-        const T t = __shfl_up(incl, o);
-        if (lane >= o) incl += t;
-    }
+    const T incl = wave_incl_scan(v);
     if (lane == 63) sh[wid] = incl;
     __syncthreads();
-    if (threadIdx.x == 0) {
-        T acc = T(0);
-        for (int w = 0; w < nw; ++w) {
-            const T t = sh[w];
-            sh[w] = acc;
-            acc += t;
-        }
-        sh[nw] = acc;
+    if (wid == 0) {
+        const T w = lane < nw ? sh[lane] : T(0);
+        const T wi = wave_incl_scan(w);
+        if (lane < nw) sh[lane] = wi - w;
+        if (lane == nw - 1) sh[nw] = wi;
     }
     __syncthreads();
     const T res = sh[wid] + incl - v;
@@ -943,11 +944,21 @@ __device__ T block_excl_scan(T v, T* sh /* >= 1024/64 + 1 entries */, T& total)
     return res;
 }
 
-template <typename T>
-__device__ T block_sum(T v, T* sh)
+// Block total of doubles (the same in every thread, fixed combination order)
+__device__ __forceinline__ double block_sum(double v, double* sh)
 {
-    T tot;
-    (void)block_excl_scan<T>(v, sh, tot);
+    const int wid = threadIdx.x >> 6;
+    const int nw = blockDim.x >> 6;
+    const double w = __ockl_wfred_add_f64(v);
+    if (lane_id() == 0) sh[wid] = w;
+    __syncthreads();
+    if (wid == 0) {
+        const double t = __ockl_wfred_add_f64(lane_id() < nw ? sh[lane_id()] : 0.0);
+        if (lane_id() == 0) sh[nw] = t;
+    }
+    __syncthreads();
+    const double tot = sh[nw];
+    __syncthreads();
     return tot;
 }
 
@@ -1009,7 +1020,7 @@ __device__ void field_block(const Params& P, const int64_t* __restrict__ rho_e,
             lsum += Tp[k];
         }
     }
-    const double st = block_sum<double>(lsum, shd);
+    const double st = block_sum(lsum, shd);
     const double eh0 = P.periodic ? -(P.fpc * (st / double(nc))) : -(P.V / P.L) - P.fpc * (st / double(nc));
     double Eh[kMaxSeg];
 #pragma unroll
@@ -1018,17 +1029,17 @@ __device__ void field_block(const Params& P, const int64_t* __restrict__ rho_e,
     const int jl = (j0 + seg - 1 < nc - 1) ? j0 + seg - 1 : nc - 1;
     if (j0 < nc) edge[threadIdx.x + 1] = Eh[jl - j0];
     __syncthreads();
-    if (threadIdx.x == 0) edge[0] = P.periodic ? edge[(nc - 1) / seg + 1] : 0.0;
-    __syncthreads();
+    // left neighbour of node 0: the last cell's half-cell field (periodic)
+    const double edge0 = P.periodic ? edge[(nc - 1) / seg + 1] : 0.0;
     bool bad = false;
 #pragma unroll
     for (int k = 0; k < kMaxSeg; ++k) {
         const int j = j0 + k;
         if (k >= seg || j >= nn) break;
-        const double left = k == 0 ? edge[threadIdx.x] : Eh[k - 1];
+        const double left = k == 0 ? (threadIdx.x == 0 ? edge0 : edge[threadIdx.x]) : Eh[k - 1];
         double e;
         if (P.periodic) {
-            const double lft = j == 0 ? edge[0] : left;
+            const double lft = j == 0 ? edge0 : left;
             e = -P.E0 + 0.5 * (lft + Eh[k]);
         } else if (j == 0) {
             e = Eh[0] - P.fpc * double(q[0]);
@@ -1210,6 +1221,7 @@ __device__ __forceinline__ void finish_column(const Params& P, const St& se, con
         }
     }
     // 3. hole filling from the tail [Np, N): small lists in LDS
+    if (nh[0] > 0 || nh[1] > 0) {
     for (int s = 0; s < 2; ++s)
         if (lds[s])
             for (int k = tid; k < kListMax / 32; k += T) sFlag[s][k] = 0u;
@@ -1262,6 +1274,7 @@ __device__ __forceinline__ void finish_column(const Params& P, const St& se, con
         __threadfence_block();
         __syncthreads();
     }
+    }   // any holes
     __syncthreads();
     // 4. append products at Np + rank (rank of the parent id among this step's)
     if (bfast) {
@@ -1286,8 +1299,8 @@ __device__ __forceinline__ void finish_column(const Params& P, const St& se, con
             put_particle(P, si, Np[1] + r, kIon, b.x, vi, uint32_t(sID[1] + r));
         }
     }
-    __threadfence();
-    __syncthreads();
+    // 5. counters (no other thread of this kernel reads them) and clearing of
+    //    the next charge buffers; nothing here waits for the particle stores
     if (tid == 0) {
         cnt->n[0] = Np[0] + nb;
         cnt->n[1] = Np[1] + nb;
@@ -1302,13 +1315,12 @@ __device__ __forceinline__ void finish_column(const Params& P, const St& se, con
         cnt->nb = 0;
         cnt->nh[0] = 0;
         cnt->nh[1] = 0;
+        cnt->step = sStep + 1;
     }
     for (int j = tid; j < P.nn; j += T) {
         if (zero_a) zero_a[j] = 0;
         if (zero_b) zero_b[j] = 0;
     }
-    __syncthreads();
-    if (tid == 0) cnt->step += 1;
 }
 
 // -------------------------------------------------------------------- load
