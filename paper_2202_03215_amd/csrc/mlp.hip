@@ -94,6 +94,18 @@ __device__ __forceinline__ void layer64(const bf16 (*act)[K], const bf16 (*wt)[K
     }
 }
 
+// tanh for BF16 activations: sign(x) (1 - t)/(1 + t), t = 2^(-2|x| log2 e),
+// on the hardware exp2 and reciprocal; x itself below 2^-10 (error x^3/3).
+// Absolute error below 3e-7, far below the BF16 rounding that follows.
+__device__ __forceinline__ float tanh_bf(float x)
+{
+    const float a = fabsf(x);
+    if (a < 0.0009765625f) return x;
+    const float t = __builtin_amdgcn_exp2f(-2.8853900817779268f * a);   // 2 log2(e)
+    const float r = (1.0f - t) * __builtin_amdgcn_rcpf(1.0f + t);
+    return copysignf(r, x);
+}
+
 // tanh of the accumulators, rounded to BF16, into a row-major LDS tile
 // (and optionally to global memory, row-major [sample][64])
 __device__ __forceinline__ void tanh_store(const f32x4 acc[4], bf16 (*act)[kH], bf16* __restrict__ g, int64_t s0,
@@ -105,7 +117,7 @@ __device__ __forceinline__ void tanh_store(const f32x4 acc[4], bf16 (*act)[kH], 
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
             const int r = 4 * (l >> 4) + i, u = nt * 16 + (l & 15);
-            const bf16 h = bf16(tanhf(acc[nt][i]));
+            const bf16 h = bf16(tanh_bf(acc[nt][i]));
             act[r][u] = h;
             if (g != nullptr && s0 + r < n) g[(s0 + r) * kH + u] = h;
         }
