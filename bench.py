@@ -27,6 +27,13 @@ import workloads as W  # noqa: E402
 
 HBM_PEAK_GBS = 8000.0   # MI355X HBM3E, GB/s
 
+# rocprofv3 FETCH_SIZE / WRITE_SIZE of the FP64 electron push kernel per launch
+# (KiB) and the counter calibration against a 512 MiB device copy (fetch x2.00,
+# write x1.00); profiles/push_counters_column_20cm_50cm.md.  Valid for the
+# kernel they were taken on only.
+PUSH_COUNTERS_KIB = {"column_20cm": (6798.0, 6904.0), "column_50cm": (79388.0, 82379.0)}
+COUNTER_CAL = (2.00, 1.00)
+
 WORKLOADS = {
     # Ne 1 Torr, periodic 20 cm, 2000 cells, 200 per cell per species (400k + 400k)
     "column_20cm": lambda: W.column_20cm(),
@@ -292,6 +299,10 @@ def main() -> int:
                    "ion_subcycle": S, "sort_interval": cfg["sort_interval"]},
         "roofline": r64["roofline"],
     }
+    if args.workload in PUSH_COUNTERS_KIB:
+        f, w = PUSH_COUNTERS_KIB[args.workload]
+        out["roofline"]["traffic"] = (f * COUNTER_CAL[0] + w * COUNTER_CAL[1]) * 1024.0
+        out["roofline"]["traffic_unit"] = "bytes per launch (calibrated FETCH_SIZE + WRITE_SIZE)"
     if r32 is not None:
         out["fp32"] = {"value": r32["value"], "ms_per_step": r32["elapsed"] * 1e3 / args.steps,
                        "dtype": "f32 particles, f64 field", "roofline": r32["roofline"],
