@@ -9,7 +9,9 @@ particle-steps per second: electrons advanced plus ions advanced (ions only
 on their subcycle steps), over exactly K timed steps with the state resident
 in device memory.  `roofline` reports the electron advance kernel (the
 dominant kernel) against the HBM peak, its duration measured with HIP events
-on the library's stream during the same timed window.  `cpu_baseline` times
+that take the start and end timestamps of each launch on the library's
+stream (hipExtLaunchKernelGGL), in an eager window of the same length right
+after the graph-replayed one.  `cpu_baseline` times
 the FP64 CPU oracle on a bounded sample of the same workload.
 """
 from __future__ import annotations
@@ -31,7 +33,7 @@ HBM_PEAK_GBS = 8000.0   # MI355X HBM3E, GB/s
 # (KiB) and the counter calibration against a 512 MiB device copy (fetch x2.00,
 # write x1.00); profiles/push_counters_column_20cm_50cm.md.  Valid for the
 # kernel they were taken on only.
-PUSH_COUNTERS_KIB = {"column_20cm": (6798.0, 6904.0), "column_50cm": (79388.0, 82379.0)}
+PUSH_COUNTERS_KIB = {"column_20cm": (6804.0, 6904.0), "column_50cm": (79427.0, 82390.0)}
 COUNTER_CAL = (2.00, 1.00)
 
 WORKLOADS = {
@@ -97,9 +99,9 @@ def measure(cfg: dict, args, tag: str) -> dict:
     ne_avg = 0.5 * (c0["n"][0] + c1["n"][0])
     ni_avg = 0.5 * (c0["n"][1] + c1["n"][1])
     value = (ne_avg * args.steps + ni_avg * ion_steps) / elapsed
-    # second timed window with HIP events around every electron-advance
-    # launch on the column's stream (eager launches: events recorded by
-    # graph nodes carry no readable time on this runtime)
+    # second timed window: every electron-advance launch carries start/end
+    # events of its own on the column's stream (eager launches: events
+    # recorded by graph nodes carry no readable time on this runtime)
     col.timer_enable(args.steps)
     torch.cuda.synchronize()
     t2 = time.perf_counter()

@@ -80,7 +80,8 @@ enum { PC_EV_NONE = 0, PC_EV_ELASTIC = 1, PC_EV_EXCITE = 2, PC_EV_IONIZE = 3,
 typedef struct pc_config {
     int32_t bc, n_cells, ppc, ion_subcycle;
     int32_t wall_mode, energy_sharing, poisson, sort_interval;
-    int32_t launch_blocks;   /* blocks of the particle kernels (0 = auto) */
+    int32_t launch_blocks;   /* blocks of the particle kernels (0 = auto: one initial particle
+                                per thread, at most 4096 blocks) */
     int32_t precision;       /* PC_FP64: FP64 particle state; PC_FP32: FP32 cell-relative
                                 state and push (field solve and collision arithmetic FP64) */
     int32_t pad1, pad2;
@@ -185,10 +186,10 @@ pc_status pc_set_events(pc_handle h, uint8_t* ev_e, int64_t len_e, uint8_t* ev_i
                         int64_t len_i);
 
 /* Kernel timer for roofline measurements: with max_launches > 0, pc_step
- * brackets each launch of the electron advance kernel (the dominant kernel:
- * gather, push, collisions, deposit) with a pair of HIP events on the
- * column's stream, up to max_launches launches (launches are then eager, not
- * graph-replayed).  The event pool is created here, never inside pc_step;
+ * times each launch of the electron advance kernel (the dominant kernel:
+ * gather, push, collisions, deposit) with a pair of HIP events that take the
+ * start and end timestamps of the launch itself (hipExtLaunchKernelGGL), up
+ * to max_launches launches (launches are then eager, not graph-replayed).  The event pool is created here, never inside pc_step;
  * 0 disables the timer and frees the pool. */
 pc_status pc_timer_enable(pc_handle h, int64_t max_launches);
 /* Wait for the recorded launches and return their summed duration [ms] and

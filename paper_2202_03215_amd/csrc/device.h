@@ -47,7 +47,7 @@ struct Counters {
     int64_t pad1[5];
 };
 
-struct Birth {           // one ionization event (64 bytes)
+struct Birth {           // one ionization event (56 bytes)
     uint32_t pid;        // id of the ionizing electron
     uint32_t slot;       // its array slot during the step
     double x;            // position

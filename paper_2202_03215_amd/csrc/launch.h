@@ -7,10 +7,13 @@ using pcdev::Params;
 using pcdev::Soa;
 using pcdev::Soa32;
 
+// t0/t1 (optional, both or neither): events that take the start and end
+// timestamps of the launch itself (hipExtLaunchKernelGGL), so that their
+// elapsed time is the kernel's duration without the queue gaps around it
 hipError_t advance(const Params& P, int species, const Soa& sp, int64_t* rho, uint8_t* ev, int64_t evlen,
-                   int grid, hipStream_t st);
+                   int grid, hipStream_t st, hipEvent_t t0 = nullptr, hipEvent_t t1 = nullptr);
 hipError_t advance(const Params& P, int species, const Soa32& sp, int64_t* rho, uint8_t* ev, int64_t evlen,
-                   int grid, hipStream_t st);
+                   int grid, hipStream_t st, hipEvent_t t0 = nullptr, hipEvent_t t1 = nullptr);
 hipError_t finish(const Params& P, const Soa& se, const Soa& si, int64_t* rho_e, int64_t* rho_i,
                   int64_t* zero_a, int64_t* zero_b, hipStream_t st);
 hipError_t finish(const Params& P, const Soa32& se, const Soa32& si, int64_t* rho_e, int64_t* rho_i,
@@ -35,7 +38,8 @@ hipError_t moments(const Params& P, const Soa32& se, const Soa32& si, int32_t cp
 hipError_t sort(const Params& P, int species, const Soa& src, const Soa& dst, int grid, hipStream_t st);
 hipError_t sort(const Params& P, int species, const Soa32& src, const Soa32& dst, int grid, hipStream_t st);
 hipError_t batch_push_e(const pcdev::ColumnDev* cols, int fp32, const pcdev::BatchItem* items, int n,
-                        const pcdev::BatchStep& b, hipStream_t st);
+                        const pcdev::BatchStep& b, hipStream_t st, hipEvent_t t0 = nullptr,
+                        hipEvent_t t1 = nullptr);
 hipError_t batch_advance_i(const pcdev::ColumnDev* cols, int fp32, const pcdev::BatchItem* items, int n,
                            const pcdev::BatchStep& b, hipStream_t st);
 hipError_t batch_finish(const pcdev::ColumnDev* cols, int n_cols, int fp32, const pcdev::BatchStep& b,
