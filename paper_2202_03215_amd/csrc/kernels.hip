@@ -1733,8 +1733,8 @@ __global__ __launch_bounds__(kAdvBlock) void k_advance_i(Params P, St sp, int64_
 {
     advance_i_chunk<EV>(P, sp, rho, ev, evlen, int(blockIdx.x), int(gridDim.x));
 }
-// Threads is the launch size (512: up to 256 VGPRs, no spills; 1024 for
-// fields above 512 kMaxSeg nodes)
+// Threads is the launch bound (512 or 768 threads: up to 256 or 168 VGPRs,
+// no spills; 1024 for fields above 768 kMaxSeg nodes)
 template <class St, int Threads>
 __global__ __launch_bounds__(Threads) void k_finish(Params P, St se, St si, int64_t* rho_e, int64_t* rho_i,
                                                     int64_t* zero_a, int64_t* zero_b)
@@ -1875,6 +1875,8 @@ static hipError_t finish_t(const Params& P, const St& se, const St& si, int64_t*
     // 28.8 microseconds per step)
     if (P.nn <= 512 * kMaxSeg)
         hipLaunchKernelGGL((k_finish<St, 512>), dim3(1), dim3(512), 0, st, P, se, si, rho_e, rho_i, zero_a, zero_b);
+    else if (P.nn <= 768 * kMaxSeg)
+        hipLaunchKernelGGL((k_finish<St, 768>), dim3(1), dim3(768), 0, st, P, se, si, rho_e, rho_i, zero_a, zero_b);
     else
         hipLaunchKernelGGL((k_finish<St, kOneBlock>), dim3(1), dim3(kOneBlock), 0, st, P, se, si, rho_e, rho_i,
                            zero_a, zero_b);

@@ -168,6 +168,16 @@ def test_step_parity_periodic_ionizing(torch_cuda):
     _run_shared_state(torch_cuda, cfg, steps=45, min_events={1: 20, 2: 5, 3: 5, 4: 5})
 
 
+@pytest.mark.parametrize("nc", [5000, 7000])
+def test_step_parity_many_nodes(torch_cuda, nc):
+    # long grids: the finish kernel runs with 768 (5000 nodes) and 1024 (7000
+    # nodes) threads, more than the 512 of the shorter columns
+    # (6 eV: no electron of the initial 20k-28k reaches the 100 eV cap)
+    cfg = W.tiny("periodic", n_cells=nc, L=nc * 1e-4, V=nc * 1e-4 * 6.0e3, ppc=4,
+                 Te0_eV=6.0, nu_w=2e8, eps_cap=100.0, sort_interval=3)
+    _run_shared_state(torch_cuda, cfg, steps=8, min_events={1: 20, 3: 3, 4: 3})
+
+
 def test_step_parity_equal_sharing_and_ions(torch_cuda):
     cfg = W.tiny("bounded", n_cells=64, L=0.0064, V=40.0, ppc=50, Te0_eV=8.0,
                  energy_sharing="equal", ion_subcycle=2, nu_w=5e7, Ti0_K=3000.0,
