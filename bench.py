@@ -11,8 +11,11 @@ in device memory.  `roofline` reports the electron advance kernel (the
 dominant kernel) against the HBM peak, its duration measured with HIP events
 that take the start and end timestamps of each launch on the library's
 stream (hipExtLaunchKernelGGL), in an eager window of the same length right
-after the graph-replayed one.  `cpu_baseline` times
-the FP64 CPU oracle on a bounded sample of the same workload.
+after the graph-replayed one.  `cpu_baseline` times the FP64 CPU oracle on
+a bounded sample of the same workload.  Further objects: `fp32` (FP32
+particles), `pair_sink` (the same column with the paper's own loss model: a
+random electron and ion removed per ionization), `batched` (64-column argon
+scan) and `fluid` (256 x 4096 fluid columns).
 """
 from __future__ import annotations
 
@@ -259,6 +262,7 @@ def main() -> int:
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-steps", type=int, default=0, help="oracle sample length (0 = auto)")
     ap.add_argument("--no-fp32", action="store_true", help="skip the FP32 variant")
+    ap.add_argument("--no-pair", action="store_true", help="skip the pair-sink variant")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched argon scan")
     ap.add_argument("--no-tune", action="store_true", help="batched scan without the autotuner")
     ap.add_argument("--batch-columns", type=int, default=64)
@@ -279,6 +283,9 @@ def main() -> int:
     cfg = WORKLOADS[args.workload]()
     r64 = measure(cfg, args, "fp64")
     r32 = measure(W.with_(cfg, precision="fp32"), args, "fp32") if not args.no_fp32 else None
+    # the paper's own sink (a random electron and ion removed per ionization)
+    pair_ok = not args.no_pair and cfg["bc"] == "periodic"
+    rpair = measure(W.with_(cfg, wall_mode="pair"), args, "pair") if pair_ok else None
     value, elapsed, ne_avg, ni_avg = r64["value"], r64["elapsed"], r64["ne"], r64["ni"]
     S = int(cfg["ion_subcycle"])
 
@@ -309,6 +316,10 @@ def main() -> int:
         out["fp32"] = {"value": r32["value"], "ms_per_step": r32["elapsed"] * 1e3 / args.steps,
                        "dtype": "f32 particles, f64 field", "roofline": r32["roofline"],
                        "speedup_vs_fp64": r32["value"] / value}
+    if rpair is not None:
+        out["pair_sink"] = {"value": rpair["value"], "ms_per_step": rpair["elapsed"] * 1e3 / args.steps,
+                            "dtype": "f64", "wall_mode": "pair", "roofline": rpair["roofline"],
+                            "relative_to_fixed_sink": rpair["value"] / value}
     if not args.no_batch:
         cfgs = W.argon_scan(args.batch_columns)
         rb = measure_batch(cfgs, args)

@@ -63,8 +63,13 @@ enum { PC_BOUNDED = 0, PC_PERIODIC = 1 };
 /* radial sink: off; fixed frequency nu_w (eq. (2)); balanced: each particle
  * is removed with probability (ionizations since the species' previous step)
  * / (its count), keeping the particle number constant on average as the
- * paper's removal of one electron-ion pair per ionization does (section II) */
-enum { PC_WALL_OFF = 0, PC_WALL_FIXED = 1, PC_WALL_BALANCED = 2 };
+ * paper's removal of one electron-ion pair per ionization does (section II);
+ * pair: the paper's model itself -- per ionization one electron and one ion,
+ * each drawn uniformly among the live ones of its species, are removed
+ * before the field solve and the products take their slots and ids (the
+ * counts stay constant; periodic columns only, ids a permutation of
+ * 0..n-1, at most 2048 ionizations per step; single columns, not batches) */
+enum { PC_WALL_OFF = 0, PC_WALL_FIXED = 1, PC_WALL_BALANCED = 2, PC_WALL_PAIR = 3 };
 enum { PC_SHARE_OPB = 0, PC_SHARE_EQUAL = 1 };
 enum { PC_ELECTRON = 0, PC_ION = 1 };
 enum { PC_FP64 = 0, PC_FP32 = 1 };

@@ -43,7 +43,7 @@
 #define FIXI ((int64_t)1 << 25)
 
 enum { ERR_RANGE = 16 };
-enum { ST_E_STEP = 0, ST_I_STEP = 1, ST_E_INIT = 2, ST_I_INIT = 3 };
+enum { ST_E_STEP = 0, ST_I_STEP = 1, ST_E_INIT = 2, ST_I_INIT = 3, ST_VICTIM_E = 4, ST_VICTIM_I = 5 };
 
 typedef struct {
     int64_t n, cap;
@@ -78,6 +78,9 @@ struct pco_column {
     int64_t nb, bcap;
     /* balanced sink: ionizations of the previous step and since the last ion step */
     int64_t births_last, births_since_ion;
+    /* pair sink: the ids removed in the last step, per species */
+    uint32_t* victims[2];
+    int64_t n_victims;
 };
 
 /* ------------------------------------------------------------------ Philox */
@@ -317,6 +320,7 @@ void pco_destroy(pco_column* c)
         free(c->sp[s].id); free(c->sp[s].ev);
     }
     free(c->E); free(c->rho_e); free(c->rho_i); free(c->iz); free(c->births);
+    free(c->victims[0]); free(c->victims[1]);
     free(c);
 }
 
@@ -687,6 +691,47 @@ static double survival(int64_t births, int64_t n)
     return 1.0 - (double)births / (double)n;
 }
 
+/* Pair sink, the paper's own loss model (section II): for every ionization
+ * one electron and one ion, picked at random over the whole column, are
+ * removed, so that the particle numbers stay constant.  Reading (the paper
+ * does not say how the random choice is made): the ids of a species are
+ * 0..N-1 (the products of an ionization take over the ids of its victims);
+ * the victim of ionization r (the step's ionizations ranked by parent id) is
+ * drawn uniformly among the particles present after the advance, without
+ * replacement: attempt t gives the id floor(w N / 2^32), w being word
+ * (t mod 4) of the Philox block with counter (r, step, t / 4, victim
+ * stream), and the first attempt that no lower rank has taken is the victim.
+ * Victims leave before the charge deposit and the field solve. */
+#define VICTIM_TRIES 65536
+static int pair_victims(pco_column* c, int s, int64_t nb, const uint32_t key[2], uint32_t* vid)
+{
+    species_t* p = &c->sp[s];
+    const uint64_t n = (uint64_t)p->n;
+    const uint32_t step = (uint32_t)c->step;
+    for (int64_t r = 0; r < nb; ++r) {
+        int found = 0;
+        for (uint32_t t = 0; t < VICTIM_TRIES && !found; ++t) {
+            uint32_t ctr[4] = {(uint32_t)r, step, t / 4u, s == PCO_ELECTRON ? ST_VICTIM_E : ST_VICTIM_I}, w[4];
+            pco_philox4x32_10(ctr, key, w);
+            const uint32_t id = (uint32_t)(((uint64_t)w[t % 4u] * n) >> 32);
+            int taken = 0;
+            for (int64_t q = 0; q < r; ++q) taken |= vid[q] == id;
+            if (!taken) { vid[r] = id; found = 1; }
+        }
+        if (!found) { c->err |= PCO_ERR_BIRTHS; return 0; }
+    }
+    /* remove the victims: find each id's index */
+    int64_t* index = (int64_t*)malloc((size_t)(n + 1) * sizeof(int64_t));
+    uint8_t* dead = (uint8_t*)calloc((size_t)n + 1, 1);
+    if (!index || !dead) { free(index); free(dead); return -3; }
+    for (int64_t k = 0; k < p->n; ++k) index[p->id[k]] = k;
+    for (int64_t r = 0; r < nb; ++r) dead[index[vid[r]]] = 1;
+    remove_dead(p, dead);
+    free(index);
+    free(dead);
+    return 0;
+}
+
 static int one_step(pco_column* c)
 {
     const uint32_t key[2] = {(uint32_t)c->cfg.seed, (uint32_t)(c->cfg.seed >> 32)};
@@ -712,20 +757,49 @@ static int one_step(pco_column* c)
         c->births_since_ion = 0;
     }
     free(dead);
-    /* ionization products: ids by rank of the parent id within the step */
+    const int pair = c->cfg.wall_mode == PCO_WALL_PAIR;
+    uint32_t* vid[2] = {NULL, NULL};
+    c->n_victims = 0;
+    if (pair && c->nb > 0) {
+        /* ids must be 0..N-1, and there must be a victim for every ionization */
+        if (e->n != c->next_id[0] || i->n != c->next_id[1]) c->err |= PCO_ERR_IDS;
+        if (c->nb > PCO_PAIR_MAX_BIRTHS || c->nb > e->n || c->nb > i->n) {
+            c->err |= PCO_ERR_BIRTHS;
+            c->nb = 0;
+        }
+    }
+    /* ionization products: ids by rank of the parent id within the step
+     * (pair sink: the ids of the victims of the same rank) */
     if (c->nb > 0) {
         qsort(c->births, (size_t)c->nb, sizeof(birth_t), cmp_birth);
+        if (pair) {
+            vid[0] = (uint32_t*)malloc((size_t)c->nb * sizeof(uint32_t));
+            vid[1] = (uint32_t*)malloc((size_t)c->nb * sizeof(uint32_t));
+            if (!vid[0] || !vid[1]) { free(vid[0]); free(vid[1]); return -3; }
+            int rc2 = pair_victims(c, PCO_ELECTRON, c->nb, key, vid[0]);
+            if (!rc2) rc2 = pair_victims(c, PCO_ION, c->nb, key, vid[1]);
+            if (rc2) { free(vid[0]); free(vid[1]); return rc2; }
+        }
         if (grow(e, e->n + c->nb) || grow(i, i->n + c->nb)) return -3;
         for (int64_t r = 0; r < c->nb; ++r) {
             const birth_t* b = &c->births[r];
             int64_t ne = e->n++, ni = i->n++;
             e->x[ne] = b->x; e->vx[ne] = b->ve[0]; e->vy[ne] = b->ve[1]; e->vz[ne] = b->ve[2];
-            e->id[ne] = (uint32_t)(c->next_id[PCO_ELECTRON] + r);
+            e->id[ne] = pair ? vid[0][r] : (uint32_t)(c->next_id[PCO_ELECTRON] + r);
             i->x[ni] = b->x; i->vx[ni] = b->vi[0]; i->vy[ni] = b->vi[1]; i->vz[ni] = b->vi[2];
-            i->id[ni] = (uint32_t)(c->next_id[PCO_ION] + r);
+            i->id[ni] = pair ? vid[1][r] : (uint32_t)(c->next_id[PCO_ION] + r);
         }
-        c->next_id[PCO_ELECTRON] += c->nb;
-        c->next_id[PCO_ION] += c->nb;
+        if (pair) {   /* kept for pco_get_victims */
+            free(c->victims[0]);
+            free(c->victims[1]);
+            c->victims[0] = vid[0];
+            c->victims[1] = vid[1];
+            c->n_victims = c->nb;
+        }
+        if (!pair) {
+            c->next_id[PCO_ELECTRON] += c->nb;
+            c->next_id[PCO_ION] += c->nb;
+        }
         if (c->next_id[0] > 0xFFFFFFFFll || c->next_id[1] > 0xFFFFFFFFll) c->err |= PCO_ERR_IDS;
         if (grow_events(e, c->next_id[0]) || grow_events(i, c->next_id[1])) return -3;
     }
@@ -807,6 +881,14 @@ int pco_set_balance(pco_column* c, int64_t births_last, int64_t births_since_ion
     c->births_last = births_last;
     c->births_since_ion = births_since_ion;
     return 0;
+}
+
+int64_t pco_get_victims(const pco_column* c, int s, uint32_t* out, int64_t cap)
+{
+    if (!c || (s != 0 && s != 1) || cap < 0) return -1;
+    int64_t m = c->n_victims < cap ? c->n_victims : cap;
+    for (int64_t r = 0; r < m; ++r) out[r] = c->victims[s][r];
+    return c->n_victims;
 }
 
 int pco_get_balance(const pco_column* c, int64_t out[2])

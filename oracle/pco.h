@@ -23,7 +23,7 @@ extern "C" {
 #endif
 
 enum { PCO_BOUNDED = 0, PCO_PERIODIC = 1 };
-enum { PCO_WALL_OFF = 0, PCO_WALL_FIXED = 1, PCO_WALL_BALANCED = 2 };
+enum { PCO_WALL_OFF = 0, PCO_WALL_FIXED = 1, PCO_WALL_BALANCED = 2, PCO_WALL_PAIR = 3 };
 enum { PCO_SHARE_OPB = 0, PCO_SHARE_EQUAL = 1 };
 enum { PCO_ELECTRON = 0, PCO_ION = 1 };
 
@@ -32,7 +32,10 @@ enum { PCO_EV_NONE = 0, PCO_EV_ELASTIC = 1, PCO_EV_EXCITE = 2, PCO_EV_IONIZE = 3
        PCO_EV_WALL = 4, PCO_EV_ABSORB = 5, PCO_EV_CX = 6, PCO_EV_NULL = 7 };
 
 /* error bits (sticky, returned by pco_errors) */
-enum { PCO_ERR_ECAP = 1, PCO_ERR_GCAP = 2, PCO_ERR_NUMAX = 4, PCO_ERR_IDS = 8 };
+enum { PCO_ERR_ECAP = 1, PCO_ERR_GCAP = 2, PCO_ERR_NUMAX = 4, PCO_ERR_IDS = 8, PCO_ERR_BIRTHS = 32 };
+
+/* pair sink: largest number of ionizations per step (victims are listed per step) */
+#define PCO_PAIR_MAX_BIRTHS 2048
 
 typedef struct pco_config {
     int32_t bc, n_cells, ppc, ion_subcycle;
@@ -79,6 +82,9 @@ int pco_set_counters(pco_column* c, int64_t step, int64_t next_e, int64_t next_i
 /* balanced sink: ionizations of the previous step and since the last ion step */
 int pco_set_balance(pco_column* c, int64_t births_last, int64_t births_since_ion);
 int pco_get_balance(const pco_column* c, int64_t out[2]);
+/* pair sink: ids removed by the last step (victim r of ionization rank r);
+ * returns their number and copies at most cap of them */
+int64_t pco_get_victims(const pco_column* c, int species, uint32_t* out, int64_t cap);
 /* current field E^n at nodes and the charges it came from */
 int pco_get_field(const pco_column* c, double* E, int64_t* rho_e, int64_t* rho_i);
 int pco_set_field(pco_column* c, const double* E);

@@ -66,6 +66,8 @@ def lib():
         L.pco_set_counters.argtypes = [P, C.c_int64, C.c_int64, C.c_int64]
         L.pco_set_balance.argtypes = [P, C.c_int64, C.c_int64]
         L.pco_get_balance.argtypes = [P, i64]
+        L.pco_get_victims.argtypes = [P, C.c_int, u32, C.c_int64]
+        L.pco_get_victims.restype = C.c_int64
         L.pco_get_field.argtypes = [P, d, i64, i64]
         L.pco_set_field.argtypes = [P, d]
         L.pco_get_events.argtypes = [P, C.c_int, u8, C.c_int64]
@@ -92,7 +94,7 @@ def make_config(cfg: dict) -> pco_config:
     s.n_cells = int(cfg["n_cells"])
     s.ppc = int(cfg["ppc"])
     s.ion_subcycle = int(cfg["ion_subcycle"])
-    s.wall_mode = {"off": 0, "fixed": 1, "balanced": 2}[cfg["wall_mode"]]
+    s.wall_mode = {"off": 0, "fixed": 1, "balanced": 2, "pair": 3}[cfg["wall_mode"]]
     s.energy_sharing = {"opb": 0, "equal": 1}[cfg["energy_sharing"]]
     s.poisson = int(cfg["poisson"])
     for k in ("L", "V", "p_torr", "Tg", "n0", "Te0_eV", "Ti0_K", "nu_w", "dt", "eps_cap",
@@ -190,6 +192,13 @@ class Oracle:
         out = np.zeros(2, dtype=np.int64)
         self._chk(lib().pco_get_balance(self.h, _ptr(out, C.c_int64)))
         return int(out[0]), int(out[1])
+
+    def victims(self, species: int) -> np.ndarray:
+        """Pair sink: ids removed by the last step, in ionization-rank order."""
+        m = int(lib().pco_get_victims(self.h, species, None, 0))
+        out = np.zeros(max(m, 1), dtype=np.uint32)
+        lib().pco_get_victims(self.h, species, _ptr(out, C.c_uint32), m)
+        return out[:m]
 
     def field(self):
         E = np.zeros(self.nn)

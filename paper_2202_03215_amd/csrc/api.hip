@@ -66,7 +66,7 @@ uint64_t thr52(double p)
 }
 
 struct Derived {
-    int nc, nn, periodic, fp32;
+    int nc, nn, periodic, fp32, pair;
     double dx, inv_dx, dti, Ng, M, c_eps, qmdt_e, qmdt_i, W, fpc, E0;
     double sig_a, sig_e0, sig_i0, mr2, sx4, si4;
     double nu_max, P_null, T_we, T_wi, P_cx;
@@ -96,8 +96,12 @@ pc_status derive(const pc_config* c, Derived* d)
     if (!(c->L > 0.0) || !(c->dt > 0.0) || c->ppc < 1 || c->ion_subcycle < 1)
         return fail(PC_ERR_INVALID_ARG, "L, dt, ppc and ion_subcycle must be positive");
     if (c->el_p != 0.5 && c->el_p != -0.5) return fail(PC_ERR_INVALID_ARG, "el_p must be +0.5 or -0.5");
-    if (c->wall_mode != PC_WALL_OFF && c->wall_mode != PC_WALL_FIXED && c->wall_mode != PC_WALL_BALANCED)
+    if (c->wall_mode != PC_WALL_OFF && c->wall_mode != PC_WALL_FIXED && c->wall_mode != PC_WALL_BALANCED &&
+        c->wall_mode != PC_WALL_PAIR)
         return fail(PC_ERR_INVALID_ARG, "wall_mode");
+    // the pair sink keeps ids dense, which electrode absorption would break
+    if (c->wall_mode == PC_WALL_PAIR && c->bc != PC_PERIODIC)
+        return fail(PC_ERR_INVALID_ARG, "the pair sink needs a periodic column");
     if (c->energy_sharing != PC_SHARE_OPB && c->energy_sharing != PC_SHARE_EQUAL)
         return fail(PC_ERR_INVALID_ARG, "energy_sharing");
     if (!(c->eps_cap > 0.0) || !(c->g_cap > 0.0) || !(c->M_amu > 0.0) || !(c->n0 > 0.0) || !(c->Tg > 0.0))
@@ -108,6 +112,7 @@ pc_status derive(const pc_config* c, Derived* d)
     d->nc = c->n_cells;
     d->periodic = c->bc == PC_PERIODIC;
     d->fp32 = c->precision == PC_FP32;
+    d->pair = c->wall_mode == PC_WALL_PAIR;
     d->nn = d->periodic ? d->nc : d->nc + 1;
     if (d->nn > pclaunch::max_nodes()) return fail(PC_ERR_INVALID_ARG, "too many nodes for the field solve");
     d->dx = c->L / double(d->nc);
@@ -176,7 +181,8 @@ pc_status derive(const pc_config* c, Derived* d)
 }
 
 struct Layout {
-    int64_t counters, soa[2][2][6], rho[2][2], E, Ef_e, Ef_i, births, holes[2], cand, cand_w, lists, bitmap, iz, sort_cnt, sort_off, total;
+    int64_t counters, soa[2][2][6], rho[2][2], E, Ef_e, Ef_i, births, holes[2], cand, cand_w, lists, bitmap, iz,
+        sort_cnt, sort_off, slot_of[2], total;
 };
 
 Layout layout(const Derived& d)
@@ -214,6 +220,8 @@ Layout layout(const Derived& d)
     L.iz = take(int64_t(d.nc) * 8);
     L.sort_cnt = take(int64_t(d.nc) * 4);
     L.sort_off = take(int64_t(d.nc) * 4);
+    L.slot_of[0] = d.pair ? take(d.cap * 4) : -1;
+    L.slot_of[1] = d.pair ? take(d.cap * 4) : -1;
     L.total = o;
     return L;
 }
@@ -243,6 +251,7 @@ struct pc_column {
     hipGraphExec_t gexec;
     int64_t gkey[6];               // bookkeeping state the graph was captured from
     int batch_member;              // owned and stepped by a batch
+    int slots_dirty;               // pair sink: the id -> slot map is rebuilt before the next step
 };
 
 namespace {
@@ -388,6 +397,9 @@ static pc_status column_init(const pc_config* cfg, const Derived& d, char* base,
     P.kw_i = thr52(d.T_wi);
     P.kcx = thr52(d.P_cx);
     P.balanced = cfg->wall_mode == PC_WALL_BALANCED;
+    P.pair = d.pair;
+    P.slot_of[0] = d.pair ? reinterpret_cast<uint32_t*>(base + L.slot_of[0]) : nullptr;
+    P.slot_of[1] = d.pair ? reinterpret_cast<uint32_t*>(base + L.slot_of[1]) : nullptr;
     P.u2v_e = d.dx / cfg->dt;
     P.u2v_i = d.dx / d.dti;
     P.efs_e = (-kQe * cfg->dt * cfg->dt) / (kMe * d.dx);
@@ -461,6 +473,7 @@ static pc_status column_init(const pc_config* cfg, const Derived& d, char* base,
     if (cfg->sort_interval > 0 && (s = run_sort(h)) != PC_OK) return cleanup(s);
     if ((s = read_counters(h)) != PC_OK) return cleanup(s);
     if (h->host_cnt.err) return cleanup(map_errors(h->host_cnt.err));
+    h->slots_dirty = d.pair;
     *out = h;
     return PC_OK;
 }
@@ -593,6 +606,11 @@ pc_status pc_step(pc_handle h, int64_t n_steps)
     // kernel timer run eagerly (graph-recorded events have no readable time)
     const bool graphs = h->use_graphs && h->st != nullptr && !h->ev[0] && !h->ev[1] &&
                         period <= 4096 && !timer_on;
+    if (h->slots_dirty) {   // pair sink: slot of every id of the current stores
+        if (h->fp32) HIPCHK(pclaunch::slot_map(h->P, h->buf32[0][h->cur[0]], h->buf32[1][h->cur[1]], h->st));
+        else HIPCHK(pclaunch::slot_map(h->P, soa_of(h, 0), soa_of(h, 1), h->st));
+        h->slots_dirty = 0;
+    }
     int64_t left = n_steps;
     while (left > 0) {
         if (graphs && h->use_graphs && left >= period) {
@@ -710,6 +728,7 @@ pc_status pc_set_state(pc_handle h, int32_t species, int64_t n, const double* x,
     }
     h->host_cnt.n[species] = n;
     h->host_cnt.err = 0;
+    h->slots_dirty = h->d.pair;
     h->host_cnt.nb = 0;
     h->host_cnt.nh[0] = h->host_cnt.nh[1] = 0;
     if ((s = write_counters(h)) != PC_OK) return s;
@@ -747,6 +766,7 @@ pc_status pc_set_counters(pc_handle h, int64_t step, int64_t next_e, int64_t nex
     h->host_cnt.next_id[1] = next_i;
     if ((s = write_counters(h)) != PC_OK) return s;
     h->step = step;
+    h->slots_dirty = h->d.pair;
     return PC_OK;
 }
 
@@ -910,6 +930,8 @@ pc_status batch_layout(const pc_config* cfgs, int32_t n, std::vector<Derived>& d
             return fail(PC_ERR_INVALID_ARG, "batch columns must share one ion subcycle");
         if (cfgs[c].sort_interval != cfgs[0].sort_interval)
             return fail(PC_ERR_INVALID_ARG, "batch columns must share one sort interval");
+        if (cfgs[c].wall_mode == PC_WALL_PAIR)
+            return fail(PC_ERR_INVALID_ARG, "the pair sink runs on single columns only");
     }
     int64_t items = 0;
     for (int32_t c = 0; c < n; ++c) items += (ds[c].cap + kMinChunk - 1) / kMinChunk;

@@ -20,6 +20,8 @@ constexpr uint32_t kStreamElectronStep = 0;
 constexpr uint32_t kStreamIonStep = 1;
 constexpr uint32_t kStreamElectronLoad = 2;
 constexpr uint32_t kStreamIonLoad = 3;
+constexpr uint32_t kStreamVictimE = 4;   // pair sink: electron victims (counter word 0: rank)
+constexpr uint32_t kStreamVictimI = 5;   // pair sink: ion victims
 
 // event codes (same values as the public header)
 constexpr uint8_t kEvNone = 0, kEvElastic = 1, kEvExcite = 2, kEvIonize = 3, kEvWall = 4,
@@ -91,7 +93,8 @@ struct Params {
     // integer forms of the per-step thresholds on the 52-bit draw k = r >> 12
     // (k < T is the same decision as (k + 1/2) 2^-52 < P for T = ceil(P 2^52 - 1/2))
     uint64_t kn_e, kw_e, kw_i, kcx;   // kw_*: fixed sink; the balanced sink derives them per step
-    int32_t balanced, pad_b;
+    int32_t balanced, pair;         // pair: one electron and one ion removed per ionization
+    uint32_t* slot_of[2];           // pair sink: slot of each id (ids dense in [0, next_id))
     // FP32 path: velocity scales (m/s per cell/step) and field scales
     double u2v_e, u2v_i;            // dx/dt, dx/dt_i
     double efs_e, efs_i;            // q dt^2/(m dx), q dt_i^2/(M dx)

@@ -1197,6 +1197,93 @@ __device__ __forceinline__ void deposit_global(const Params& P, const St& st, in
     atomicAdd((unsigned long long*)&rho[j1], (unsigned long long)a);
 }
 
+// ------------------------------------------------------------- pair sink
+// Section II keeps the particle number constant: for every ionization of the
+// step one electron and one ion, each chosen at random among the live
+// particles of its species, leave the column.  Ids stay dense in [0, N): the
+// products of ionization r (ranked by parent id) take the slots and ids of
+// victims r, so the arrays keep their length and order.  Victim r of a
+// species takes the first attempt t = 0, 1, ... whose id, floor(w N / 2^32)
+// with w word t mod 4 of the Philox block (r, step, t / 4, victim stream),
+// no lower rank has taken.
+__device__ __forceinline__ uint32_t victim_draw(const Params& P, int species, uint32_t r, uint32_t step,
+                                                uint32_t t, uint64_t n)
+{
+    const U4 w = philox10(r, step, t >> 2, species == kElectron ? kStreamVictimE : kStreamVictimI, P.key0,
+                          P.key1);
+    const uint32_t q = t & 3u;
+    const uint32_t word = q == 0 ? w.a : (q == 1 ? w.b : (q == 2 ? w.c : w.d));
+    return uint32_t((uint64_t(word) * n) >> 32);
+}
+
+constexpr uint32_t kVictimTries = 1u << 16;
+
+// removes a particle's CIC charge (the deposit of deposit_global, negated)
+template <class St>
+__device__ __forceinline__ void undeposit_global(const Params& P, const St& st, int64_t* rho, double xk)
+{
+    int64_t a;
+    const int j = key_cell(P, st, xk, a);
+    int j1 = j + 1;
+    if (P.periodic && j1 == P.nc) j1 = 0;
+    atomicAdd((unsigned long long*)&rho[j], (unsigned long long)(a - kUnit));
+    atomicAdd((unsigned long long*)&rho[j1], (unsigned long long)(-a));
+}
+
+// Victims of the step's nb ionizations (nb <= kListMax): ids and slots in
+// LDS, their charge taken out of rho_e / rho_i before the field solve.
+template <class St>
+__device__ void pair_victims(const Params& P, const St& se, const St& si, int64_t* rho_e, int64_t* rho_i,
+                             int64_t nb, uint32_t step, const int64_t id_range[2], uint32_t (*vid)[kListMax],
+                             uint32_t (*vslot)[kListMax])
+{
+    __shared__ int coll;
+    const int tid = threadIdx.x, T = blockDim.x;
+    if (tid == 0) coll = 0;
+    for (int64_t r = tid; r < nb; r += T)
+        for (int s = 0; s < 2; ++s) vid[s][r] = victim_draw(P, s, uint32_t(r), step, 0u, uint64_t(id_range[s]));
+    __syncthreads();
+    // first attempts that repeat a lower rank's (rare: about nb^2 / 2N per step)
+    for (int64_t r = tid; r < nb; r += T)
+        for (int s = 0; s < 2; ++s)
+            for (int64_t q = 0; q < r; ++q)
+                if (vid[s][q] == vid[s][r]) {
+                    coll = 1;
+                    break;
+                }
+    __syncthreads();
+    // the finish kernels run at least 512 threads: lanes 0 and 64 (two
+    // waves) redo the ranks of one species each, in rank order
+    if (coll && (tid == 0 || tid == 64)) {
+        const int s = tid == 0 ? 0 : 1;
+        for (int64_t r = 0; r < nb; ++r)
+            for (uint32_t t = 0;; ++t) {
+                if (t == kVictimTries) {   // bounded search (nb <= N makes it unreachable in practice)
+                    set_err(P, kErrBirths);
+                    break;
+                }
+                const uint32_t id = victim_draw(P, s, uint32_t(r), step, t, uint64_t(id_range[s]));
+                bool taken = false;
+                for (int64_t q = 0; q < r; ++q) taken = taken || vid[s][q] == id;
+                if (!taken) {
+                    vid[s][r] = id;
+                    break;
+                }
+            }
+    }
+    __syncthreads();
+    for (int64_t r = tid; r < nb; r += T) {
+        for (int s = 0; s < 2; ++s) {
+            const St& sp = s == 0 ? se : si;
+            const uint32_t slot = P.slot_of[s][vid[s][r]];
+            vslot[s][r] = slot;
+            undeposit_global(P, sp, s == 0 ? rho_e : rho_i, pos_key(P, sp, slot));
+        }
+    }
+    __threadfence();      // the field loads below read the corrected charges
+    __syncthreads();
+}
+
 template <class St>
 __device__ __forceinline__ void finish_column(const Params& P, const St& se, const St& si, int64_t* rho_e,
                                               int64_t* rho_i, int64_t* zero_a, int64_t* zero_b)
@@ -1211,7 +1298,7 @@ __device__ __forceinline__ void finish_column(const Params& P, const St& se, con
     // the charge loads of the field solve go first: they depend on nothing
     // else, and the loads below wait for the counters
     FieldLoads fl;
-    if (P.poisson) fl = field_load(P, rho_e, rho_i);
+    if (P.poisson && !P.pair) fl = field_load(P, rho_e, rho_i);
     Counters* cnt = P.cnt;
     // the step's counters (the same words for every thread)
     const int64_t n_in[2] = {cnt->n[0], cnt->n[1]};
@@ -1227,7 +1314,13 @@ __device__ __forceinline__ void finish_column(const Params& P, const St& se, con
         Np[s] = n_in[s] - nh[s];
         lds[s] = nh[s] <= kListMax;
     }
-    if (Np[0] + nb > P.cap || Np[1] + nb > P.cap) {
+    if (P.pair) {
+        // victims are listed in LDS, and there must be as many live particles
+        if (nb > kListMax || nb > id_in[0] || nb > id_in[1]) {
+            if (tid == 0) set_err(P, kErrBirths);
+            nb = 0;
+        }
+    } else if (Np[0] + nb > P.cap || Np[1] + nb > P.cap) {
         if (tid == 0) set_err(P, kErrCapacity);
         nb = 0;
     }
@@ -1258,6 +1351,12 @@ __device__ __forceinline__ void finish_column(const Params& P, const St& se, con
         for (int k = tid; k < kOneBlock / 32; k += T) sUpd[k] = 0u;
     }
     if (tid == 0) sC[0] = sC[1] = sC[2] = sC[3] = 0u;
+    // 0. pair sink: victims chosen and their charge removed (the hole lists
+    //    are empty in this mode, so their LDS arrays hold the victims)
+    if (P.pair) {
+        pair_victims(P, se, si, rho_e, rho_i, nb, uint32_t(step_in), id_in, sL1, sL2);
+        if (P.poisson) fl = field_load(P, rho_e, rho_i);
+    }
     // 1. field E^{n+1}.  An ionization adds an electron and an ion at the same
     //    position, so the net charge -- and the field -- do not depend on this
     //    step's products: the solve needs only the charges deposited by the
@@ -1403,8 +1502,13 @@ __device__ __forceinline__ void finish_column(const Params& P, const St& se, con
             if (k < nb) {
                 int64_t r = 0;
                 for (int64_t q = 0; q < nb; ++q) r += sPid[q] < bpid[m] ? 1 : 0;
-                put_particle(P, se, Np[0] + r, kElectron, bx[m], bve[m], uint32_t(id_in[0] + r));
-                put_particle(P, si, Np[1] + r, kIon, bx[m], bvi[m], uint32_t(id_in[1] + r));
+                if (P.pair) {   // into victim r's slots, with its ids
+                    put_particle(P, se, sL2[0][r], kElectron, bx[m], bve[m], sL1[0][r]);
+                    put_particle(P, si, sL2[1][r], kIon, bx[m], bvi[m], sL1[1][r]);
+                } else {
+                    put_particle(P, se, Np[0] + r, kElectron, bx[m], bve[m], uint32_t(id_in[0] + r));
+                    put_particle(P, si, Np[1] + r, kIon, bx[m], bvi[m], uint32_t(id_in[1] + r));
+                }
             }
         }
     } else {
@@ -1414,18 +1518,24 @@ __device__ __forceinline__ void finish_column(const Params& P, const St& se, con
             ionize(P, b, step, vs, ve, vi);
             int64_t r = 0;
             for (int64_t q = 0; q < nb; ++q) r += P.births[q].pid < b.pid ? 1 : 0;
-            put_particle(P, se, Np[0] + r, kElectron, b.x, ve, uint32_t(id_in[0] + r));
-            put_particle(P, si, Np[1] + r, kIon, b.x, vi, uint32_t(id_in[1] + r));
+            if (P.pair) {
+                put_particle(P, se, sL2[0][r], kElectron, b.x, ve, sL1[0][r]);
+                put_particle(P, si, sL2[1][r], kIon, b.x, vi, sL1[1][r]);
+            } else {
+                put_particle(P, se, Np[0] + r, kElectron, b.x, ve, uint32_t(id_in[0] + r));
+                put_particle(P, si, Np[1] + r, kIon, b.x, vi, uint32_t(id_in[1] + r));
+            }
         }
     }
     // 5. counters (no other thread of this kernel reads them) and clearing of
     //    the next charge buffers; nothing here waits for the particle stores
     if (tid == 0) {
-        cnt->n[0] = Np[0] + nb;
-        cnt->n[1] = Np[1] + nb;
-        cnt->next_id[0] = id_in[0] + nb;
-        cnt->next_id[1] = id_in[1] + nb;
-        if (id_in[0] + nb > 0xFFFFFFFFll || id_in[1] + nb > 0xFFFFFFFFll) set_err(P, kErrIds);
+        const int64_t grow = P.pair ? 0 : nb;   // pair sink: products replace the victims
+        cnt->n[0] = Np[0] + grow;
+        cnt->n[1] = Np[1] + grow;
+        cnt->next_id[0] = id_in[0] + grow;
+        cnt->next_id[1] = id_in[1] + grow;
+        if (id_in[0] + grow > 0xFFFFFFFFll || id_in[1] + grow > 0xFFFFFFFFll) set_err(P, kErrIds);
         // ionization tallies of the balanced sink (an ion step consumed the
         // tally since the previous one)
         const int64_t since = (step_in % P.ion_subcycle == 0) ? 0 : cnt->births_since_ion;
@@ -1504,6 +1614,25 @@ __global__ __launch_bounds__(256) void k_deposit32(Params P, Soa32 sp, int64_t n
     if (P.periodic && j1 == P.nc) j1 = 0;
     atomicAdd((unsigned long long*)&rho[j], (unsigned long long)(kUnit - a));
     atomicAdd((unsigned long long*)&rho[j1], (unsigned long long)a);
+}
+
+// pair sink: the slot of every id (ids must be a permutation of 0..n-1)
+template <class St>
+__global__ __launch_bounds__(256) void k_slot_map(Params P, St se, St si)
+{
+    for (int s = 0; s < 2; ++s) {
+        const int64_t n = P.cnt->n[s];
+        if (P.cnt->next_id[s] != n) {
+            if (blockIdx.x == 0 && threadIdx.x == 0) set_err(P, kErrIds);
+            continue;
+        }
+        const uint32_t* __restrict__ ids = s == 0 ? se.id : si.id;
+        for (int64_t k = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; k < n; k += int64_t(gridDim.x) * blockDim.x) {
+            const uint32_t id = ids[k];
+            if (int64_t(id) < n) P.slot_of[s][id] = uint32_t(k);
+            else set_err(P, kErrIds);
+        }
+    }
 }
 
 __global__ void k_fill_i64(int64_t* p, int64_t n, int64_t v)
@@ -1714,7 +1843,10 @@ __device__ __forceinline__ void sort_scatter_chunk(const Params& P, const St& sr
             if (li >= 0 && li < kWindow) pos = bw[li] + atomicAdd(&cw[li], 1);
             else pos = atomicAdd(&P.sort_off[c], 1);
         }
-        if (act) copy_particle(dst, pos, src, i);
+        if (act) {
+            copy_particle(dst, pos, src, i);
+            if (P.pair) P.slot_of[S][src.id[i]] = uint32_t(pos);
+        }
     }
 }
 
@@ -2006,6 +2138,21 @@ hipError_t from64(const Params& P, const Soa& src, const Soa32& dst, int64_t n, 
     return hipGetLastError();
 }
 
+template <class St>
+static hipError_t slot_map_t(const Params& P, const St& se, const St& si, hipStream_t st)
+{
+    if (!P.pair) return hipSuccess;
+    hipLaunchKernelGGL(k_slot_map<St>, dim3(grid_for(P.cap, 256, 4096)), dim3(256), 0, st, P, se, si);
+    return hipGetLastError();
+}
+hipError_t slot_map(const Params& P, const Soa& se, const Soa& si, hipStream_t st)
+{
+    return slot_map_t(P, se, si, st);
+}
+hipError_t slot_map(const Params& P, const Soa32& se, const Soa32& si, hipStream_t st)
+{
+    return slot_map_t(P, se, si, st);
+}
 hipError_t fill_i64(int64_t* p, int64_t n, int64_t v, hipStream_t st)
 {
     if (n == 0) return hipSuccess;

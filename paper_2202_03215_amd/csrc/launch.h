@@ -46,6 +46,8 @@ hipError_t batch_finish(const pcdev::ColumnDev* cols, int n_cols, int fp32, cons
                         hipStream_t st);
 hipError_t batch_sort(const pcdev::ColumnDev* cols, int n_cols, int fp32, int species, const pcdev::BatchItem* items,
                       int n, int cur, hipStream_t st);
+hipError_t slot_map(const Params& P, const Soa& se, const Soa& si, hipStream_t st);
+hipError_t slot_map(const Params& P, const Soa32& se, const Soa32& si, hipStream_t st);
 int max_nodes();
 
 }  // namespace pclaunch

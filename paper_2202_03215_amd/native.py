@@ -141,7 +141,7 @@ def make_config(cfg: dict) -> pc_config:
     s.n_cells = int(cfg["n_cells"])
     s.ppc = int(cfg["ppc"])
     s.ion_subcycle = int(cfg["ion_subcycle"])
-    s.wall_mode = {"off": 0, "fixed": 1, "balanced": 2}[cfg["wall_mode"]]
+    s.wall_mode = {"off": 0, "fixed": 1, "balanced": 2, "pair": 3}[cfg["wall_mode"]]
     s.energy_sharing = {"opb": 0, "equal": 1}[cfg["energy_sharing"]]
     s.poisson = int(cfg["poisson"])
     s.sort_interval = int(cfg.get("sort_interval", 0))

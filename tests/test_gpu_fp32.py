@@ -99,6 +99,14 @@ def test_fp32_step_parity_periodic_ionizing(torch_cuda):
     _step_parity(cfg, steps=45)
 
 
+def test_fp32_step_parity_pair_sink(torch_cuda):
+    # pair sink on FP32 stores: victims are chosen from integer draws, so the
+    # same ids leave and the products take them as in the FP64 oracle
+    cfg = W.tiny("periodic", n_cells=101, L=0.0101, V=0.0101 * 6.0e3, ppc=40, Te0_eV=6.0,
+                 wall_mode="pair", ion_subcycle=3, sort_interval=4, precision="fp32")
+    _step_parity(cfg, steps=40)
+
+
 def test_fp32_initial_load_matches_fp64(torch_cuda):
     cfg = W.tiny("periodic", n_cells=200, L=0.02, V=2.0, ppc=50)
     a = _column(cfg)

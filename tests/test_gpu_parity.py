@@ -194,6 +194,24 @@ def test_step_parity_balanced_sink(torch_cuda):
     assert tot[4] > 0
 
 
+def test_step_parity_pair_sink(torch_cuda):
+    # the paper's own sink: per ionization a random electron and ion leave
+    # and the products take their slots and ids; the GPU arrays are first
+    # stored in a shuffled order (the id -> slot map is rebuilt from them)
+    cfg = W.tiny("periodic", n_cells=101, L=0.0101, V=0.0101 * 6.0e3, ppc=40, Te0_eV=6.0,
+                 wall_mode="pair", ion_subcycle=3, sort_interval=4)
+
+    def setup(col):
+        rng = np.random.default_rng(2)
+        for s in (ELECTRON, ION):
+            x, vx, vy, vz, ids = (a.cpu().numpy() for a in col.get_state(s))
+            p = rng.permutation(x.size)
+            col.set_state(s, x[p], vx[p], vy[p], vz[p], ids[p])
+
+    tot = _run_shared_state(torch_cuda, cfg, steps=40, setup=setup, min_events={1: 50, 3: 20})
+    assert tot[4] == 0
+
+
 def test_step_parity_long_loss_and_birth_lists(torch_cuda):
     # more than 2048 losses and ionizations in one step: the finish kernel
     # takes its global-scratch paths instead of the LDS lists

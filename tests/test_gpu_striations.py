@@ -10,6 +10,11 @@ E0 lambda; the 3 % criterion is met exactly when the mode agrees), growth
 rates within 10 %, and phase velocities towards the cathode (negative)
 within 15 % of each other (the window still holds the end of the growth;
 over 1e6 steps the saturated phase velocities agree within 2 %).
+
+The paper's own sink (one random electron and one random ion removed per
+ionization) against the balanced sink, FP64, same length: the particle
+numbers stay exactly constant, and the striations have the same dominant
+mode, growth rates within 10 % and phase velocities within 15 %.
 """
 import numpy as np
 import pytest
@@ -47,3 +52,22 @@ def test_fp32_striations_match_fp64(torch_cuda):
     assert a["phase_velocity"] < 0 and b["phase_velocity"] < 0
     assert abs(a["phase_velocity"] - b["phase_velocity"]) <= 0.15 * abs(a["phase_velocity"])
     assert a["growth"] > 0 and abs(a["growth"] - b["growth"]) <= 0.10 * a["growth"]
+
+
+def test_pair_sink_striations_match_balanced_sink(torch_cuda):
+    from paper_2202_03215_amd import physics as PH
+    steps, every = 200_000, 1000
+    out = {}
+    for wm in ("pair", "balanced"):
+        cfg = W.with_(W.column_20cm(), wall_mode=wm)
+        res = PH.run(cfg, steps, every)
+        s = PH.striation_summary(res, cfg, 0.75 * steps * cfg["dt"])
+        s["growth"] = PH.growth_rate(res, s["mode"])
+        print(wm, s)
+        out[wm] = (s, res["counts"])
+    (a, counts), (b, _) = out["pair"], out["balanced"]
+    assert np.all(counts == 400_000), counts.min()
+    assert a["modulation"] > 0.3 and b["modulation"] > 0.3
+    assert a["mode"] == b["mode"]
+    assert a["phase_velocity"] < 0 and abs(a["phase_velocity"] - b["phase_velocity"]) <= 0.15 * abs(b["phase_velocity"])
+    assert a["growth"] > 0 and abs(a["growth"] - b["growth"]) <= 0.10 * b["growth"]

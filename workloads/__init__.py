@@ -26,7 +26,9 @@ Config keys (all SI unless noted):
   Te0_eV, Ti0_K initial electron temperature [eV] and ion temperature [K]
   wall_mode     "off" | "fixed": radial-loss sink with frequency nu_w [s^-1] |
                 "balanced": removal probability = ionizations since the species'
-                previous step / its count (constant particle number on average)
+                previous step / its count (constant particle number on average) |
+                "pair": per ionization one random electron and one random ion
+                removed, the products take their ids (constant counts; periodic)
   dt            electron time step [s]; ions advance every ion_subcycle steps
   eps_cap       energy [eV] up to which the null-collision bound is taken
   g_cap         relative-speed bound [m/s] of the ion null-collision method
