@@ -92,6 +92,11 @@ typedef struct pc_config {
     int32_t pad1, pad2;
     double L, V, p_torr, Tg, n0, Te0_eV, Ti0_K, nu_w, dt, eps_cap, g_cap, capacity;
     double M_amu, el_A, el_B, el_p, ex_U, ex_smax, iz_U, iz_smax, cx_sigma, opb_w;
+    /* bounded columns (section V): cathode emission current density emit_J
+     * [A/m^2] (0 = none) of electrons at temperature emit_T [eV]; series
+     * resistance circuit_R [ohm m^2] between the source V and the anode
+     * (0 = anode held at V).  Single columns only. */
+    double emit_J, emit_T, circuit_R;
     uint64_t seed;
 } pc_config;
 
@@ -114,6 +119,10 @@ typedef struct pc_counts {
     uint32_t pad;
     int64_t births_last;     /* ionizations of the previous step (balanced sink) */
     int64_t births_since_ion; /* ionizations since the last ion step (balanced sink) */
+    double V_anode;          /* anode potential of the last field solve [V] (circuit) */
+    double J_cond;           /* conduction current density of the last step [A/m^2] */
+    int64_t vsum_ion;        /* ions' sum of v_x at their last step, 2^-20 m/s units */
+    double emit_carry;       /* fraction of an emitted electron carried to the next step */
 } pc_counts;
 
 typedef struct pc_column* pc_handle;
@@ -175,6 +184,11 @@ pc_status pc_set_state(pc_handle h, int32_t species, int64_t n, const double* x,
 
 /* Set the step index and next ids (blocking). */
 pc_status pc_set_counters(pc_handle h, int64_t step, int64_t next_e, int64_t next_i);
+/* External circuit and emission state (section V), for restarts and parity
+ * checks (blocking): anode potential, the ions' held v_x sum (as in
+ * pc_counts) and the emission carry. */
+pc_status pc_set_circuit(pc_handle h, double V_anode, int64_t vsum_ion, double emit_carry);
+
 /* Set the ionization tallies of the balanced sink (blocking). */
 pc_status pc_set_balance(pc_handle h, int64_t births_last, int64_t births_since_ion);
 

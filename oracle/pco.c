@@ -43,7 +43,8 @@
 #define FIXI ((int64_t)1 << 25)
 
 enum { ERR_RANGE = 16 };
-enum { ST_E_STEP = 0, ST_I_STEP = 1, ST_E_INIT = 2, ST_I_INIT = 3, ST_VICTIM_E = 4, ST_VICTIM_I = 5 };
+enum { ST_E_STEP = 0, ST_I_STEP = 1, ST_E_INIT = 2, ST_I_INIT = 3, ST_VICTIM_E = 4, ST_VICTIM_I = 5,
+       ST_EMIT = 6 };
 
 typedef struct {
     int64_t n, cap;
@@ -81,6 +82,9 @@ struct pco_column {
     /* pair sink: the ids removed in the last step, per species */
     uint32_t* victims[2];
     int64_t n_victims;
+    /* section V: cathode emission and the external circuit */
+    double emit_n, emit_sig, circ_a, circ_jf, Jc, carry;
+    int64_t vs_e, vs_ia, vs_i;   /* sums of v_x in 2^-20 m/s units */
 };
 
 /* ------------------------------------------------------------------ Philox */
@@ -272,6 +276,13 @@ pco_column* pco_create(const pco_config* cfg)
     c->fpc = QE * c->W / FIX / EPS0;
     c->E0 = cfg->V / cfg->L;
     c->Vb = cfg->V;
+    /* section V: emitted electrons per step J dt / (e W), their thermal speed,
+     * the gap's R eps0 / (L dt) and the current density of one unit of the
+     * v_x sums, e W / L 2^-20 */
+    c->emit_n = cfg->emit_J * cfg->dt / (QE * c->W);
+    c->emit_sig = sqrt(QE * cfg->emit_T / ME);
+    c->circ_a = cfg->circuit_R * EPS0 / (cfg->L * cfg->dt);
+    c->circ_jf = QE * c->W / cfg->L / 1048576.0;
     c->sig_a = sqrt(KB * cfg->Tg / c->M);
     c->sig_e0 = sqrt(cfg->Te0_eV * QE / ME);
     c->sig_i0 = sqrt(KB * cfg->Ti0_K / c->M);
@@ -536,6 +547,7 @@ static int electron_pass(pco_column* c, uint8_t* dead, const uint32_t key[2])
         double Ex = gather(c, x);
         vx = vx + c->qmdt_e * Ex;
         x = x + vx * c->dt;
+        const double vpush = vx;   /* for the circuit's conduction current */
         int lost = boundary(c, &x, &ev);
         if (!lost) {
             uint32_t ctr[4] = {id, step, 0u, ST_E_STEP}, w[4];
@@ -614,6 +626,7 @@ static int electron_pass(pco_column* c, uint8_t* dead, const uint32_t key[2])
         p->x[k] = x;
         p->vx[k] = vx;
         dead[k] = (uint8_t)lost;
+        if (!lost && c->cfg.circuit_R > 0.0) c->vs_e += (int64_t)(vpush * 1048576.0);
         p->ev[id] = ev;
     }
     return 0;
@@ -630,6 +643,7 @@ static void ion_pass(pco_column* c, uint8_t* dead, const uint32_t key[2])
         double Ex = gather(c, x);
         vx = vx + c->qmdt_i * Ex;
         x = x + vx * c->dti;
+        const double vpush = vx;   /* before charge exchange */
         int lost = boundary(c, &x, &ev);
         if (!lost) {
             uint32_t ctr[4] = {id, step, 0u, ST_I_STEP}, w[4];
@@ -664,6 +678,7 @@ static void ion_pass(pco_column* c, uint8_t* dead, const uint32_t key[2])
         p->x[k] = x;
         p->vx[k] = vx;
         dead[k] = (uint8_t)lost;
+        if (!lost && c->cfg.circuit_R > 0.0) c->vs_ia += (int64_t)(vpush * 1048576.0);
         p->ev[id] = ev;
     }
 }
@@ -805,8 +820,72 @@ static int one_step(pco_column* c)
     }
     c->births_last = c->nb;
     c->births_since_ion += c->nb;
+    /* external circuit (section V): the anode potential of this field solve
+     * from the conduction current of the step -- v_x after the push of the
+     * particles still present, ions from their last subcycle step -- and the
+     * gap's displacement current, backward Euler in time:
+     * V' (1 + a) = V_source + R J + a V with a = R eps0 / (L dt) */
+    if (c->cfg.circuit_R > 0.0) {
+        const int64_t vi = ion_step ? c->vs_ia : c->vs_i;
+        const double J = c->circ_jf * (double)(vi - c->vs_e);
+        c->Vb = (c->cfg.V + c->cfg.circuit_R * J + c->circ_a * c->Vb) / (1.0 + c->circ_a);
+        c->Jc = J;
+        c->vs_e = 0;
+        if (ion_step) {
+            c->vs_i = c->vs_ia;
+            c->vs_ia = 0;
+        }
+    }
     field_update(c);
+    /* cathode emission (section V): J dt / (e W) electrons per step with the
+     * fraction carried over, after the field solve; each has a flux-weighted
+     * half-Maxwellian velocity at emit_T (v_x from a Rayleigh draw, v_y, v_z
+     * normal) and has flown a uniform fraction of a step from x = 0; ids follow
+     * the products' and the draws come from the new id's own stream */
+    if (c->cfg.emit_J > 0.0) {
+        const double ce = c->carry + c->emit_n;
+        const int64_t n_emit = (int64_t)floor(ce);
+        c->carry = ce - (double)n_emit;
+        if (grow(e, e->n + n_emit)) return -3;
+        for (int64_t r = 0; r < n_emit; ++r) {
+            const uint32_t id = (uint32_t)(c->next_id[PCO_ELECTRON] + r);
+            uint32_t ctr[4] = {id, (uint32_t)c->step, 0u, ST_EMIT}, w[4];
+            pco_philox4x32_10(ctr, key, w);
+            const double vx = c->emit_sig * sqrt(-2.0 * log(u52(w[0], w[1])));
+            double x = vx * c->dt * u52(w[2], w[3]);
+            if (!(x < c->L)) x = 0.0;
+            kstream_t ks;
+            ks_init(&ks, key, id, (uint32_t)c->step, ST_EMIT);
+            double g[2];
+            gauss2(&ks, g);
+            const int64_t m = e->n++;
+            e->x[m] = x; e->vx[m] = vx; e->vy[m] = c->emit_sig * g[0]; e->vz[m] = c->emit_sig * g[1];
+            e->id[m] = id;
+        }
+        c->next_id[PCO_ELECTRON] += n_emit;
+        if (c->next_id[0] > 0xFFFFFFFFll) c->err |= PCO_ERR_IDS;
+        if (grow_events(e, c->next_id[0])) return -3;
+    }
     c->step += 1;
+    return 0;
+}
+
+int pco_set_circuit(pco_column* c, double V_anode, int64_t vsum_ion, double emit_carry)
+{
+    if (!c || !(emit_carry >= 0.0 && emit_carry < 1.0)) return -1;
+    c->Vb = V_anode;
+    c->vs_i = vsum_ion;
+    c->carry = emit_carry;
+    return 0;
+}
+
+int pco_get_circuit(const pco_column* c, double out[3], int64_t* vsum_ion)
+{
+    if (!c || !vsum_ion) return -1;
+    out[0] = c->Vb;
+    out[1] = c->Jc;
+    out[2] = c->carry;
+    *vsum_ion = c->vs_i;
     return 0;
 }
 

@@ -42,6 +42,9 @@ typedef struct pco_config {
     int32_t wall_mode, energy_sharing, poisson, pad0;
     double L, V, p_torr, Tg, n0, Te0_eV, Ti0_K, nu_w, dt, eps_cap, g_cap;
     double M_amu, el_A, el_B, el_p, ex_U, ex_smax, iz_U, iz_smax, cx_sigma, opb_w;
+    /* bounded column of section V: cathode emission current density [A/m^2]
+     * at temperature emit_T [eV]; series resistance [ohm m^2] to the source V */
+    double emit_J, emit_T, circuit_R;
     uint64_t seed;
 } pco_config;
 
@@ -85,6 +88,11 @@ int pco_get_balance(const pco_column* c, int64_t out[2]);
 /* pair sink: ids removed by the last step (victim r of ionization rank r);
  * returns their number and copies at most cap of them */
 int64_t pco_get_victims(const pco_column* c, int species, uint32_t* out, int64_t cap);
+/* section V state: anode potential, ions' held v_x sum (2^-20 m/s units) and
+ * the emission carry; get returns (V_anode, last conduction current density,
+ * carry) and the ion sum */
+int pco_set_circuit(pco_column* c, double V_anode, int64_t vsum_ion, double emit_carry);
+int pco_get_circuit(const pco_column* c, double out[3], int64_t* vsum_ion);
 /* current field E^n at nodes and the charges it came from */
 int pco_get_field(const pco_column* c, double* E, int64_t* rho_e, int64_t* rho_i);
 int pco_set_field(pco_column* c, const double* E);

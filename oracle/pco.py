@@ -23,7 +23,8 @@ class pco_config(C.Structure):
                 ("energy_sharing", C.c_int32), ("poisson", C.c_int32), ("pad0", C.c_int32)] + \
         [(k, C.c_double) for k in ("L", "V", "p_torr", "Tg", "n0", "Te0_eV", "Ti0_K", "nu_w",
                                    "dt", "eps_cap", "g_cap", "M_amu", "el_A", "el_B", "el_p",
-                                   "ex_U", "ex_smax", "iz_U", "iz_smax", "cx_sigma", "opb_w")] + \
+                                   "ex_U", "ex_smax", "iz_U", "iz_smax", "cx_sigma", "opb_w",
+                                   "emit_J", "emit_T", "circuit_R")] + \
         [("seed", C.c_uint64)]
 
 
@@ -67,6 +68,8 @@ def lib():
         L.pco_set_balance.argtypes = [P, C.c_int64, C.c_int64]
         L.pco_get_balance.argtypes = [P, i64]
         L.pco_get_victims.argtypes = [P, C.c_int, u32, C.c_int64]
+        L.pco_set_circuit.argtypes = [P, C.c_double, C.c_int64, C.c_double]
+        L.pco_get_circuit.argtypes = [P, d, i64]
         L.pco_get_victims.restype = C.c_int64
         L.pco_get_field.argtypes = [P, d, i64, i64]
         L.pco_set_field.argtypes = [P, d]
@@ -101,6 +104,9 @@ def make_config(cfg: dict) -> pco_config:
               "g_cap", "M_amu", "el_A", "el_B", "el_p", "ex_U", "ex_smax", "iz_U", "iz_smax",
               "cx_sigma", "opb_w"):
         setattr(s, k, float(cfg[k]))
+    s.emit_J = float(cfg.get("emit_J", 0.0))
+    s.emit_T = float(cfg.get("emit_T", 0.5))
+    s.circuit_R = float(cfg.get("circuit_R", 0.0))
     s.seed = int(cfg["seed"])
     return s
 
@@ -192,6 +198,17 @@ class Oracle:
         out = np.zeros(2, dtype=np.int64)
         self._chk(lib().pco_get_balance(self.h, _ptr(out, C.c_int64)))
         return int(out[0]), int(out[1])
+
+    def set_circuit(self, V_anode: float, vsum_ion: int, emit_carry: float):
+        self._chk(lib().pco_set_circuit(self.h, float(V_anode), int(vsum_ion), float(emit_carry)))
+
+    def circuit(self) -> dict:
+        """Section V state: anode potential, last conduction current density,
+        emission carry and the ions' held v_x sum."""
+        out = np.zeros(3)
+        vs = np.zeros(1, dtype=np.int64)
+        self._chk(lib().pco_get_circuit(self.h, _ptr(out, C.c_double), _ptr(vs, C.c_int64)))
+        return dict(V_anode=float(out[0]), J_cond=float(out[1]), emit_carry=float(out[2]), vsum_ion=int(vs[0]))
 
     def victims(self, species: int) -> np.ndarray:
         """Pair sink: ids removed by the last step, in ionization-rank order."""

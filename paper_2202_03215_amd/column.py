@@ -106,7 +106,9 @@ class Column:
         N.check(N.lib().pc_get_counts(self.h, C.byref(c)))
         return dict(n=(int(c.n[0]), int(c.n[1])), next_id=(int(c.next_id[0]), int(c.next_id[1])),
                     step=int(c.step), errors=int(c.errors),
-                    balance=(int(c.births_last), int(c.births_since_ion)))
+                    balance=(int(c.births_last), int(c.births_since_ion)),
+                    circuit=(float(c.V_anode), int(c.vsum_ion), float(c.emit_carry)),
+                    J_cond=float(c.J_cond))
 
     # ------------------------------------------------------ stand-alone ops
     def _empty(self, n, dtype):
@@ -162,6 +164,10 @@ class Column:
 
     def set_balance(self, births_last: int, births_since_ion: int) -> None:
         N.check(N.lib().pc_set_balance(self.h, int(births_last), int(births_since_ion)))
+
+    def set_circuit(self, V_anode: float, vsum_ion: int, emit_carry: float) -> None:
+        """Anode potential, ions' held v_x sum and emission carry (section V)."""
+        N.check(N.lib().pc_set_circuit(self.h, float(V_anode), int(vsum_ion), float(emit_carry)))
 
     def get_field(self):
         E = self._empty(self.nn, torch.float64)

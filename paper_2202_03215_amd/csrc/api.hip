@@ -102,6 +102,10 @@ pc_status derive(const pc_config* c, Derived* d)
     // the pair sink keeps ids dense, which electrode absorption would break
     if (c->wall_mode == PC_WALL_PAIR && c->bc != PC_PERIODIC)
         return fail(PC_ERR_INVALID_ARG, "the pair sink needs a periodic column");
+    if (!(c->emit_J >= 0.0) || !(c->circuit_R >= 0.0) || (c->emit_J > 0.0 && !(c->emit_T > 0.0)))
+        return fail(PC_ERR_INVALID_ARG, "emit_J and circuit_R must be >= 0, emit_T > 0 with emission");
+    if ((c->emit_J > 0.0 || c->circuit_R > 0.0) && c->bc != PC_BOUNDED)
+        return fail(PC_ERR_INVALID_ARG, "cathode emission and the external circuit need a bounded column");
     if (c->energy_sharing != PC_SHARE_OPB && c->energy_sharing != PC_SHARE_EQUAL)
         return fail(PC_ERR_INVALID_ARG, "energy_sharing");
     if (!(c->eps_cap > 0.0) || !(c->g_cap > 0.0) || !(c->M_amu > 0.0) || !(c->n0 > 0.0) || !(c->Tg > 0.0))
@@ -398,6 +402,13 @@ static pc_status column_init(const pc_config* cfg, const Derived& d, char* base,
     P.kcx = thr52(d.P_cx);
     P.balanced = cfg->wall_mode == PC_WALL_BALANCED;
     P.pair = d.pair;
+    P.emit = cfg->emit_J > 0.0;
+    P.circuit = cfg->circuit_R > 0.0;
+    P.emit_n = cfg->emit_J * cfg->dt / (kQe * d.W);
+    P.emit_sig = std::sqrt(kQe * cfg->emit_T / kMe);
+    P.circ_R = cfg->circuit_R;
+    P.circ_a = cfg->circuit_R * kEps0 / (cfg->L * cfg->dt);
+    P.circ_jf = kQe * d.W / cfg->L / 1048576.0;
     P.slot_of[0] = d.pair ? reinterpret_cast<uint32_t*>(base + L.slot_of[0]) : nullptr;
     P.slot_of[1] = d.pair ? reinterpret_cast<uint32_t*>(base + L.slot_of[1]) : nullptr;
     P.u2v_e = d.dx / cfg->dt;
@@ -439,6 +450,7 @@ static pc_status column_init(const pc_config* cfg, const Derived& d, char* base,
     std::memset(&h->host_cnt, 0, sizeof(Counters));
     h->host_cnt.n[0] = h->host_cnt.n[1] = d.n0;
     h->host_cnt.next_id[0] = h->host_cnt.next_id[1] = d.n0;
+    h->host_cnt.V = cfg->V;
     if ((s = write_counters(h)) != PC_OK) return cleanup(s);
     hipError_t e = hipSuccess;
     for (int sp = 0; sp < 2 && e == hipSuccess; ++sp)
@@ -675,7 +687,23 @@ pc_status pc_get_counts(pc_handle h, pc_counts* out)
     out->pad = 0;
     out->births_last = h->host_cnt.births_last;
     out->births_since_ion = h->host_cnt.births_since_ion;
+    out->V_anode = h->host_cnt.V;
+    out->J_cond = h->host_cnt.J;
+    out->vsum_ion = h->host_cnt.vsum_i;
+    out->emit_carry = h->host_cnt.carry;
     return PC_OK;
+}
+
+pc_status pc_set_circuit(pc_handle h, double V_anode, int64_t vsum_ion, double emit_carry)
+{
+    if (!h || !(emit_carry >= 0.0 && emit_carry < 1.0) || !(V_anode == V_anode))
+        return fail(PC_ERR_INVALID_ARG, "bad circuit state");
+    pc_status s = read_counters(h);
+    if (s != PC_OK) return s;
+    h->host_cnt.V = V_anode;
+    h->host_cnt.vsum_i = vsum_ion;
+    h->host_cnt.carry = emit_carry;
+    return write_counters(h);
 }
 
 pc_status pc_set_balance(pc_handle h, int64_t births_last, int64_t births_since_ion)
@@ -932,6 +960,8 @@ pc_status batch_layout(const pc_config* cfgs, int32_t n, std::vector<Derived>& d
             return fail(PC_ERR_INVALID_ARG, "batch columns must share one sort interval");
         if (cfgs[c].wall_mode == PC_WALL_PAIR)
             return fail(PC_ERR_INVALID_ARG, "the pair sink runs on single columns only");
+        if (cfgs[c].emit_J > 0.0 || cfgs[c].circuit_R > 0.0)
+            return fail(PC_ERR_INVALID_ARG, "cathode emission and the circuit run on single columns only");
     }
     int64_t items = 0;
     for (int32_t c = 0; c < n; ++c) items += (ds[c].cap + kMinChunk - 1) / kMinChunk;

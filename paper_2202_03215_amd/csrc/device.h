@@ -22,6 +22,7 @@ constexpr uint32_t kStreamElectronLoad = 2;
 constexpr uint32_t kStreamIonLoad = 3;
 constexpr uint32_t kStreamVictimE = 4;   // pair sink: electron victims (counter word 0: rank)
 constexpr uint32_t kStreamVictimI = 5;   // pair sink: ion victims
+constexpr uint32_t kStreamEmit = 6;      // cathode emission (counter word 0: the new id)
 
 // event codes (same values as the public header)
 constexpr uint8_t kEvNone = 0, kEvElastic = 1, kEvExcite = 2, kEvIonize = 3, kEvWall = 4,
@@ -46,7 +47,14 @@ struct Counters {
     int64_t nh[2];       // losses recorded in the current step
     int64_t births_last;       // balanced sink: ionizations of the previous step
     int64_t births_since_ion;  // balanced sink: ionizations since the last ion step
-    int64_t pad1[5];
+    // bounded column with an external circuit and cathode emission (section V)
+    double V;            // anode potential of the next field solve [V]
+    double J;            // conduction current density of the last step [A/m^2]
+    int64_t vsum_e;      // electrons' sum of v_x (2^-20 m/s units) of the current step
+    int64_t vsum_ia;     // ions' sum of v_x accumulated by the current ion step
+    int64_t vsum_i;      // ions' sum of v_x of the last ion step (held between ion steps)
+    double carry;        // fractional emitted electrons carried to the next step
+    int64_t pad1[2];
 };
 
 struct Birth {           // one ionization event (56 bytes)
@@ -95,6 +103,13 @@ struct Params {
     uint64_t kn_e, kw_e, kw_i, kcx;   // kw_*: fixed sink; the balanced sink derives them per step
     int32_t balanced, pair;         // pair: one electron and one ion removed per ionization
     uint32_t* slot_of[2];           // pair sink: slot of each id (ids dense in [0, next_id))
+    // bounded column, section V: cathode emission and a series resistor
+    int32_t emit, circuit;
+    double emit_n;                  // emitted electrons per step, J_e0 dt / (e W)
+    double emit_sig;                // sqrt(e T_c / m_e): thermal speed of emitted electrons
+    double circ_R;                  // series resistance [ohm m^2]
+    double circ_a;                  // R eps0 / (L dt)
+    double circ_jf;                 // e W / L per 2^-20 m/s: current density of one velocity unit
     // FP32 path: velocity scales (m/s per cell/step) and field scales
     double u2v_e, u2v_i;            // dx/dt, dx/dt_i
     double efs_e, efs_i;            // q dt^2/(m dx), q dt_i^2/(M dx)

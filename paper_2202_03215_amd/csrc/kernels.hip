@@ -127,6 +127,17 @@ __device__ __forceinline__ int64_t wave_append(bool flag, int64_t* counter)
     return flag ? int64_t(base) + int64_t(lanes_below(m)) : -1;
 }
 
+// Conduction-current sums of the external circuit (section V): v_x of the
+// particles alive after their push, truncated to 2^-20 m/s units, so that
+// the sum does not depend on the order of the atomics.
+__device__ __forceinline__ int64_t vunits(double v) { return int64_t(v * 1048576.0); }
+__device__ __forceinline__ void add_current(int64_t* sum, bool alive, double vx)
+{
+    const uint64_t q = alive ? uint64_t(vunits(vx)) : 0ull;
+    const uint64_t t = __ockl_wfred_add_u64(q);
+    if (lane_id() == 0 && t != 0ull) atomicAdd((unsigned long long*)sum, (unsigned long long)t);
+}
+
 // contiguous chunk kb of nb equal (64-aligned) chunks of a particle array
 __device__ __forceinline__ void chunk_range(int64_t n, int kb, int nb, int64_t& beg, int64_t& end)
 {
@@ -214,6 +225,9 @@ __device__ __forceinline__ void store_v(const Params& P, const Soa32& s, uint32_
     s.vy[i] = float(vy / k);
     s.vz[i] = float(vz / k);
 }
+// position key of a position x [m] for put_particle: x itself (FP64) or x / dx (FP32)
+__device__ __forceinline__ double key_of_x(const Params&, const Soa&, double x) { return x; }
+__device__ __forceinline__ double key_of_x(const Params& P, const Soa32&, double x) { return x * P.inv_dx; }
 // position key of a particle: x [m] (FP64) or cell + offset (FP32, exact in FP64)
 __device__ __forceinline__ double pos_key(const Params&, const Soa& s, uint32_t i) { return s.x[i]; }
 __device__ __forceinline__ double pos_key(const Params&, const Soa32& s, uint32_t i)
@@ -516,6 +530,7 @@ __device__ __forceinline__ void push_e_chunk(const Params& P, const Soa& sp, int
                 }
             }
         }
+        if (P.circuit) add_current(&P.cnt->vsum_e, alive, vx);
         deposit_wave(P, win, wbase, rho, alive, jn, an);
     }
     __syncthreads();
@@ -563,6 +578,7 @@ __device__ __forceinline__ void advance_i_chunk(const Params& P, const Soa& sp, 
         bool alive = false;
         int jn = 0;
         int64_t an = 0;
+        double vpush = 0.0;   // v_x after the push, before charge exchange
         if (act) {
             double x = sp.x[i];
             double vx = sp.vx[i];
@@ -572,6 +588,7 @@ __device__ __forceinline__ void advance_i_chunk(const Params& P, const Soa& sp, 
             const double Ex = E[j] + f * (E[j + 1] - E[j]);
             vx = vx + P.qmdt_i * Ex;
             x = x + vx * P.dti;
+            vpush = vx;
             uint8_t code = kEvNone;
             alive = apply_boundary(P, x, code);
             if (alive) {
@@ -616,6 +633,7 @@ __device__ __forceinline__ void advance_i_chunk(const Params& P, const Soa& sp, 
             if (hp < P.max_holes) P.holes[kIon][hp] = uint32_t(i);
             else set_err(P, kErrLosses);
         }
+        if (P.circuit) add_current(&P.cnt->vsum_ia, alive, vpush);
         deposit_wave(P, win, wbase, rho, alive, jn, an);
     }
     __syncthreads();
@@ -765,6 +783,7 @@ __device__ __forceinline__ void push_e_chunk(const Params& P, const Soa32& sp, i
                 }
             }
         }
+        if (P.circuit) add_current(&P.cnt->vsum_e, alive, double(u) * P.u2v_e);
         deposit_wave(P, win, wbase, rho, alive, jn, an);
     }
     __syncthreads();
@@ -803,6 +822,7 @@ __device__ __forceinline__ void advance_i_chunk(const Params& P, const Soa32& sp
         bool alive = false;
         int jn = 0;
         int64_t an = 0;
+        float upush = 0.0f;   // v_x after the push, before charge exchange
         if (act) {
             int c = sp.cell[i];
             float off = sp.off[i];
@@ -810,6 +830,7 @@ __device__ __forceinline__ void advance_i_chunk(const Params& P, const Soa32& sp
             const uint32_t id = sp.id[i];
             uint8_t code = kEvNone;
             alive = push32(P, P.Ef_i, c, off, u, code);
+            upush = u;
             if (alive) {
                 const U4 w = philox10(id, step, 0u, kStreamIonStep, P.key0, P.key1);
                 const uint64_t k0 = draw52(w.a, w.b);
@@ -852,6 +873,7 @@ __device__ __forceinline__ void advance_i_chunk(const Params& P, const Soa32& sp
             if (hp < P.max_holes) P.holes[kIon][hp] = uint32_t(i);
             else set_err(P, kErrLosses);
         }
+        if (P.circuit) add_current(&P.cnt->vsum_ia, alive, double(upush) * P.u2v_i);
         deposit_wave(P, win, wbase, rho, alive, jn, an);
     }
     __syncthreads();
@@ -1032,7 +1054,7 @@ __device__ __forceinline__ FieldLoads field_load(const Params& P, const int64_t*
 }
 
 __device__ void field_solve(const Params& P, const FieldLoads& fl, double* __restrict__ E,
-                            double* __restrict__ phi, bool ghost, bool scaled)
+                            double* __restrict__ phi, bool ghost, bool scaled, double V)
 {
     __shared__ int64_t shi[kOneBlock / 64 + 1];
     __shared__ double shd[kOneBlock / 64 + 1];
@@ -1081,7 +1103,7 @@ __device__ void field_solve(const Params& P, const FieldLoads& fl, double* __res
         }
     }
     const double st = block_sum(lsum, shd);
-    const double eh0 = P.periodic ? -(P.fpc * (st / double(nc))) : -(P.V / P.L) - P.fpc * (st / double(nc));
+    const double eh0 = P.periodic ? -(P.fpc * (st / double(nc))) : -(V / P.L) - P.fpc * (st / double(nc));
     double Eh[kMaxSeg];
 #pragma unroll
     for (int k = 0; k < kMaxSeg; ++k) Eh[k] = eh0 + P.fpc * Tp[k];
@@ -1134,7 +1156,7 @@ __device__ void field_solve(const Params& P, const FieldLoads& fl, double* __res
         for (int k = 0; k < kMaxSeg; ++k) {
             const int j = j0 + k;
             if (k >= seg || j >= nn) break;
-            phi[j] = j == 0 ? 0.0 : (!P.periodic && j == nc ? P.V : -P.dx * run);
+            phi[j] = j == 0 ? 0.0 : (!P.periodic && j == nc ? V : -P.dx * run);
             if (j < nc) run += Eh[k];
         }
     }
@@ -1144,9 +1166,9 @@ __global__ __launch_bounds__(kOneBlock) void k_field(Params P, const int64_t* rh
                                                      double* E, double* phi, int ghost)
 {
     if (P.poisson || phi != nullptr || !ghost) {
-        field_solve(P, field_load(P, rho_e, rho_i), E, phi, ghost != 0, false);
+        field_solve(P, field_load(P, rho_e, rho_i), E, phi, ghost != 0, false, P.circuit ? P.cnt->V : P.V);
     } else {
-        const double e0 = P.periodic ? -P.E0 : -(P.V / P.L);
+        const double e0 = P.periodic ? -P.E0 : -((P.circuit ? P.cnt->V : P.V) / P.L);
         for (int j = threadIdx.x; j <= P.nn; j += blockDim.x) E[j] = e0;
     }
 }
@@ -1357,15 +1379,25 @@ __device__ __forceinline__ void finish_column(const Params& P, const St& se, con
         pair_victims(P, se, si, rho_e, rho_i, nb, uint32_t(step_in), id_in, sL1, sL2);
         if (P.poisson) fl = field_load(P, rho_e, rho_i);
     }
+    // 0b. external circuit (section V): the anode potential of this solve from
+    //    the step's conduction current (particles' v_x after their push; ions
+    //    from their last subcycle step) and the displacement current of the
+    //    gap, backward Euler: V' (1 + a) = V_source + R J + a V, a = R eps0/(L dt)
+    double Vf = P.V, Jc = 0.0;
+    if (P.circuit) {
+        const int64_t vi = step_in % P.ion_subcycle == 0 ? cnt->vsum_ia : cnt->vsum_i;
+        Jc = P.circ_jf * double(vi - cnt->vsum_e);
+        Vf = (P.V + P.circ_R * Jc + P.circ_a * cnt->V) / (1.0 + P.circ_a);
+    }
     // 1. field E^{n+1}.  An ionization adds an electron and an ion at the same
     //    position, so the net charge -- and the field -- do not depend on this
     //    step's products: the solve needs only the charges deposited by the
     //    advance kernels and runs first.
     //    FP32 particles also get the field scaled to cells per step^2.
     if (P.poisson) {
-        field_solve(P, fl, P.E, nullptr, true, P.Ef_e != nullptr);
+        field_solve(P, fl, P.E, nullptr, true, P.Ef_e != nullptr, Vf);
     } else {
-        const double e0 = P.periodic ? -P.E0 : -(P.V / P.L);
+        const double e0 = P.periodic ? -P.E0 : -(Vf / P.L);
         for (int j = tid; j <= P.nn; j += T) {
             P.E[j] = e0;
             if (P.Ef_e != nullptr) {
@@ -1527,15 +1559,49 @@ __device__ __forceinline__ void finish_column(const Params& P, const St& se, con
             }
         }
     }
+    // 4b. cathode emission (section V): J_e0 dt / (e W) electrons per step, the
+    //     fraction carried over; flux-weighted half-Maxwellian at T_c entering
+    //     at x = 0, each a uniform fraction of a step in flight; ids after the
+    //     products', draws from the new id's own stream
+    const int64_t grow = P.pair ? 0 : nb;   // pair sink: products replace the victims
+    const double ce = P.emit ? cnt->carry + P.emit_n : 0.0;
+    int64_t n_emit = int64_t(floor(ce));
+    if (Np[0] + grow + n_emit > P.cap) {
+        if (tid == 0) set_err(P, kErrCapacity);
+        n_emit = 0;
+    }
+    for (int64_t r = tid; r < n_emit; r += T) {
+        const uint32_t id = uint32_t(id_in[0] + grow + r);
+        const U4 w = philox10(id, uint32_t(step_in), 0u, kStreamEmit, P.key0, P.key1);
+        double v[3];
+        v[0] = P.emit_sig * sqrt(-2.0 * log(unif52(w.a, w.b)));
+        double x = v[0] * P.dt * unif52(w.c, w.d);
+        if (!(x < P.L)) x = 0.0;
+        WordStream ws(id, uint32_t(step_in), kStreamEmit, P.key0, P.key1);
+        double g0, g1;
+        normal_pair(ws, g0, g1);
+        v[1] = P.emit_sig * g0;
+        v[2] = P.emit_sig * g1;
+        put_particle(P, se, Np[0] + grow + r, kElectron, key_of_x(P, se, x), v, id);
+    }
     // 5. counters (no other thread of this kernel reads them) and clearing of
     //    the next charge buffers; nothing here waits for the particle stores
     if (tid == 0) {
-        const int64_t grow = P.pair ? 0 : nb;   // pair sink: products replace the victims
-        cnt->n[0] = Np[0] + grow;
+        cnt->n[0] = Np[0] + grow + n_emit;
         cnt->n[1] = Np[1] + grow;
-        cnt->next_id[0] = id_in[0] + grow;
+        cnt->next_id[0] = id_in[0] + grow + n_emit;
         cnt->next_id[1] = id_in[1] + grow;
-        if (id_in[0] + grow > 0xFFFFFFFFll || id_in[1] + grow > 0xFFFFFFFFll) set_err(P, kErrIds);
+        if (id_in[0] + grow + n_emit > 0xFFFFFFFFll || id_in[1] + grow > 0xFFFFFFFFll) set_err(P, kErrIds);
+        if (P.emit) cnt->carry = ce - double(n_emit);
+        if (P.circuit) {
+            cnt->V = Vf;
+            cnt->J = Jc;
+            cnt->vsum_e = 0;
+            if (step_in % P.ion_subcycle == 0) {
+                cnt->vsum_i = cnt->vsum_ia;
+                cnt->vsum_ia = 0;
+            }
+        }
         // ionization tallies of the balanced sink (an ion step consumed the
         // tally since the previous one)
         const int64_t since = (step_in % P.ion_subcycle == 0) ? 0 : cnt->births_since_ion;

@@ -23,6 +23,7 @@ ELECTRON, ION = 0, 1
 # every exported symbol of include/*.h
 EXPORTS = ("pc_query_sizes", "pc_init_column", "pc_step", "pc_deposit", "pc_solve_field",
            "pc_moments", "pc_get_counts", "pc_get_state", "pc_set_state", "pc_set_counters", "pc_set_balance",
+           "pc_set_circuit",
            "pc_get_field", "pc_set_field", "pc_set_events", "pc_timer_enable",
            "pc_timer_read", "pc_sync", "pc_destroy",
            "pc_query_batch_sizes", "pc_init_batch", "pc_batch_step", "pc_batch_column",
@@ -49,7 +50,7 @@ class pc_config(C.Structure):
         [(k, C.c_double) for k in ("L", "V", "p_torr", "Tg", "n0", "Te0_eV", "Ti0_K", "nu_w",
                                    "dt", "eps_cap", "g_cap", "capacity", "M_amu", "el_A",
                                    "el_B", "el_p", "ex_U", "ex_smax", "iz_U", "iz_smax",
-                                   "cx_sigma", "opb_w")] + \
+                                   "cx_sigma", "opb_w", "emit_J", "emit_T", "circuit_R")] + \
         [("seed", C.c_uint64)]
 
 
@@ -63,7 +64,8 @@ class pc_sizes(C.Structure):
 class pc_counts(C.Structure):
     _fields_ = [("n", C.c_int64 * 2), ("next_id", C.c_int64 * 2), ("step", C.c_int64),
                 ("errors", C.c_uint32), ("pad", C.c_uint32), ("births_last", C.c_int64),
-                ("births_since_ion", C.c_int64)]
+                ("births_since_ion", C.c_int64), ("V_anode", C.c_double), ("J_cond", C.c_double),
+                ("vsum_ion", C.c_int64), ("emit_carry", C.c_double)]
 
 
 class pc_tuning(C.Structure):
@@ -96,6 +98,7 @@ def lib() -> C.CDLL:
         "pc_set_state": [P, I32, I64, P, P, P, P, P],
         "pc_set_counters": [P, I64, I64, I64],
         "pc_set_balance": [P, I64, I64],
+        "pc_set_circuit": [P, C.c_double, I64, C.c_double],
         "pc_get_field": [P, P, P, P],
         "pc_set_field": [P, P],
         "pc_set_events": [P, P, I64, P, I64],
@@ -152,6 +155,9 @@ def make_config(cfg: dict) -> pc_config:
               "cx_sigma", "opb_w"):
         setattr(s, k, float(cfg[k]))
     s.capacity = float(cfg.get("capacity", 1.25))
+    s.emit_J = float(cfg.get("emit_J", 0.0))
+    s.emit_T = float(cfg.get("emit_T", 0.5))
+    s.circuit_R = float(cfg.get("circuit_R", 0.0))
     s.seed = int(cfg["seed"])
     return s
 

@@ -36,6 +36,7 @@ def copy_gpu_to_oracle(col, orc):
     orc.set_field(E.cpu().numpy())
     orc.set_counters(c["step"], c["next_id"][0], c["next_id"][1])
     orc.set_balance(*c["balance"])
+    orc.set_circuit(*c["circuit"])
 
 
 def compare_states(col, orc, L, vth, exact_v=False):

@@ -107,6 +107,14 @@ def test_fp32_step_parity_pair_sink(torch_cuda):
     _step_parity(cfg, steps=40)
 
 
+def test_fp32_step_parity_hot_cathode_and_circuit(torch_cuda):
+    # section V on FP32 stores: emitted electrons (integer counts, same draws)
+    # and the circuit's anode potential from FP32 velocities
+    cfg = W.with_(W.small_bounded(), emit_J=10.0, emit_T=0.5, circuit_R=10.0, nu_w=1.0e6, ion_subcycle=4,
+                  precision="fp32")
+    _step_parity(cfg, steps=40)
+
+
 def test_fp32_initial_load_matches_fp64(torch_cuda):
     cfg = W.tiny("periodic", n_cells=200, L=0.02, V=2.0, ppc=50)
     a = _column(cfg)

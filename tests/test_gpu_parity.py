@@ -116,7 +116,7 @@ def test_initial_load(torch_cuda, cfg):
 
 
 # ------------------------------------------------------- per-step parity (P5)
-def _run_shared_state(torch, cfg, steps, min_events=None, setup=None):
+def _run_shared_state(torch, cfg, steps, min_events=None, setup=None, check=None):
     col = _column(cfg)
     orc = Oracle(cfg, init=False)
     if setup is not None:
@@ -150,6 +150,8 @@ def _run_shared_state(torch, cfg, steps, min_events=None, setup=None):
         assert np.array_equal(reg.cpu().numpy(), reo), f"step {k}: electron charge"
         assert np.array_equal(rig.cpu().numpy(), rio), f"step {k}: ion charge"
         assert field_close(Eg.cpu().numpy(), Eo), f"step {k}: field"
+        if check is not None:
+            check(col, orc, k)
     if min_events:
         for code, m in min_events.items():
             assert tot[code] >= m, f"only {tot[code]} events of type {code}: {tot}"
@@ -210,6 +212,26 @@ def test_step_parity_pair_sink(torch_cuda):
 
     tot = _run_shared_state(torch_cuda, cfg, steps=40, setup=setup, min_events={1: 50, 3: 20})
     assert tot[4] == 0
+
+
+def test_step_parity_hot_cathode_and_circuit(torch_cuda):
+    # section V: cathode emission (10 A/m^2, about 3 electrons per step) and
+    # a 10 ohm m^2 series resistor; ions every 4 steps (their held current)
+    cfg = W.with_(W.small_bounded(), emit_J=10.0, emit_T=0.5, circuit_R=10.0, nu_w=1.0e6, ion_subcycle=4)
+    seen = []
+
+    def check(col, orc, k):
+        g = col.counts()
+        o = orc.circuit()
+        V, vs, carry = g["circuit"]
+        assert abs(V - o["V_anode"]) <= 1e-12 * abs(cfg["V"]), (k, V, o["V_anode"])
+        assert abs(g["J_cond"] - o["J_cond"]) <= 1e-12 * max(abs(o["J_cond"]), 1.0), k
+        assert vs == o["vsum_ion"] and carry == o["emit_carry"], k
+        seen.append((g["next_id"][0], V))
+
+    _run_shared_state(torch_cuda, cfg, steps=40, check=check, min_events={1: 20})
+    assert seen[-1][0] - seen[0][0] >= 100               # emitted electrons took new ids
+    assert abs(seen[-1][1] - cfg["V"]) > 0.01             # the resistor moved the anode potential
 
 
 def test_step_parity_long_loss_and_birth_lists(torch_cuda):

@@ -35,6 +35,10 @@ Config keys (all SI unless noted):
   energy_sharing "opb" | "equal" split of the ionization excess energy
   poisson       1 = self-consistent field, 0 = imposed field only (swarm mode)
   sort_interval steps between counting sorts (0 = never; no effect on physics)
+  emit_J, emit_T bounded columns: cathode emission current density [A/m^2]
+                and temperature of the emitted electrons [eV] (section V)
+  circuit_R     bounded columns: series resistance [ohm m^2] between the
+                source V and the anode (0 = anode held at V)
   capacity      particle-array capacity as a multiple of the initial count
   precision     "fp64" | "fp32" particle state on the GPU (the oracle is FP64)
   seed          Philox key
@@ -63,7 +67,7 @@ ARGON = dict(gas="Ar", M_amu=39.948,
 _COMMON = dict(p_torr=1.0, Tg=300.0, Te0_eV=2.0, Ti0_K=300.0,
                wall_mode="fixed", nu_w=1.0e5, dt=1.0e-11, ion_subcycle=20,
                eps_cap=100.0, g_cap=1.0e4, energy_sharing="opb", poisson=1,
-               sort_interval=20, capacity=1.25, seed=1)
+               sort_interval=20, capacity=1.25, emit_J=0.0, emit_T=0.5, circuit_R=0.0, seed=1)
 
 
 def _mk(gas: dict, **kw) -> dict:
@@ -79,6 +83,18 @@ def small_bounded(seed: int = 1) -> dict:
     for a 1 cm radius, dt = 1e-11 s, ions every 20 steps, 2000 steps."""
     return _mk(NEON, bc="bounded", n_cells=400, L=0.04, V=40.0, n0=1.0e14,
                ppc=50, seed=seed)
+
+
+def hot_cathode_15cm(seed: int = 1, ppc: int = 100) -> dict:
+    """The bounded column of section V: neon, 1 Torr, 15 cm gap, source 270 V
+    through a 10 ohm m^2 resistor, hot cathode emitting 10 A/m^2 (electrons at
+    0.5 eV), fixed radial loss frequency 1e6 /s; 1500 cells, n0 = 1e15 m^-3
+    (near the density the discharge settles at), 100 per cell per species
+    (150k + 150k).  Ions cross the cathode sheath fast: g_cap 5e4 m/s with
+    ions every 10 steps keeps their null-collision probability below 0.1."""
+    return _mk(NEON, bc="bounded", n_cells=1500, L=0.15, V=270.0, n0=1.0e15, ppc=ppc,
+               nu_w=1.0e6, emit_J=10.0, emit_T=0.5, circuit_R=10.0, capacity=3.0, g_cap=5.0e4,
+               ion_subcycle=10, seed=seed)
 
 
 def column_20cm(seed: int = 1, ppc: int = 200) -> dict:
