@@ -14,8 +14,9 @@ stream (hipExtLaunchKernelGGL), in an eager window of the same length right
 after the graph-replayed one.  `cpu_baseline` times the FP64 CPU oracle on
 a bounded sample of the same workload.  Further objects: `fp32` (FP32
 particles), `pair_sink` (the same column with the paper's own loss model: a
-random electron and ion removed per ionization), `batched` (64-column argon
-scan) and `fluid` (256 x 4096 fluid columns).
+random electron and ion removed per ionization), `section_v` (the bounded
+15 cm column with a hot cathode and a series resistor), `batched` (64-column
+argon scan) and `fluid` (256 x 4096 fluid columns).
 """
 from __future__ import annotations
 
@@ -263,6 +264,8 @@ def main() -> int:
     ap.add_argument("--cpu-steps", type=int, default=0, help="oracle sample length (0 = auto)")
     ap.add_argument("--no-fp32", action="store_true", help="skip the FP32 variant")
     ap.add_argument("--no-pair", action="store_true", help="skip the pair-sink variant")
+    ap.add_argument("--no-section-v", action="store_true",
+                    help="skip the bounded hot-cathode column with the external circuit")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched argon scan")
     ap.add_argument("--no-tune", action="store_true", help="batched scan without the autotuner")
     ap.add_argument("--batch-columns", type=int, default=64)
@@ -320,6 +323,12 @@ def main() -> int:
         out["pair_sink"] = {"value": rpair["value"], "ms_per_step": rpair["elapsed"] * 1e3 / args.steps,
                             "dtype": "f64", "wall_mode": "pair", "roofline": rpair["roofline"],
                             "relative_to_fixed_sink": rpair["value"] / value}
+    if not args.no_section_v:
+        hc = W.hot_cathode_15cm()
+        rv = measure(hc, args, "section_v")
+        out["section_v"] = {"workload": "hot_cathode_15cm", "value": rv["value"],
+                            "ms_per_step": rv["elapsed"] * 1e3 / args.steps, "dtype": "f64",
+                            "electrons": int(rv["ne"]), "ions": int(rv["ni"]), "roofline": rv["roofline"]}
     if not args.no_batch:
         cfgs = W.argon_scan(args.batch_columns)
         rb = measure_batch(cfgs, args)

@@ -186,7 +186,7 @@ pc_status derive(const pc_config* c, Derived* d)
 
 struct Layout {
     int64_t counters, soa[2][2][6], rho[2][2], E, Ef_e, Ef_i, births, holes[2], cand, cand_w, lists, bitmap, iz,
-        sort_cnt, sort_off, slot_of[2], total;
+        sort_cnt, sort_off, slot_of[2], csum, total;
 };
 
 Layout layout(const Derived& d)
@@ -226,6 +226,7 @@ Layout layout(const Derived& d)
     L.sort_off = take(int64_t(d.nc) * 4);
     L.slot_of[0] = d.pair ? take(d.cap * 4) : -1;
     L.slot_of[1] = d.pair ? take(d.cap * 4) : -1;
+    L.csum = take(128 * 8);
     L.total = o;
     return L;
 }
@@ -409,6 +410,7 @@ static pc_status column_init(const pc_config* cfg, const Derived& d, char* base,
     P.circ_R = cfg->circuit_R;
     P.circ_a = cfg->circuit_R * kEps0 / (cfg->L * cfg->dt);
     P.circ_jf = kQe * d.W / cfg->L / 1048576.0;
+    P.csum = reinterpret_cast<int64_t*>(base + L.csum);
     P.slot_of[0] = d.pair ? reinterpret_cast<uint32_t*>(base + L.slot_of[0]) : nullptr;
     P.slot_of[1] = d.pair ? reinterpret_cast<uint32_t*>(base + L.slot_of[1]) : nullptr;
     P.u2v_e = d.dx / cfg->dt;
@@ -456,6 +458,7 @@ static pc_status column_init(const pc_config* cfg, const Derived& d, char* base,
     for (int sp = 0; sp < 2 && e == hipSuccess; ++sp)
         for (int b = 0; b < 2 && e == hipSuccess; ++b) e = pclaunch::fill_i64(h->rho[sp][b], d.nn, 0, h->st);
     if (e == hipSuccess) e = pclaunch::fill_i64(P.iz, d.nc, 0, h->st);
+    if (e == hipSuccess) e = pclaunch::fill_i64(P.csum, 128, 0, h->st);
     if (e == hipSuccess) e = pclaunch::fill_i64(reinterpret_cast<int64_t*>(P.sort_cnt), (d.nc + 1) / 2, 0, h->st);
     if (d.fp32) {
         // FP32 columns: the loader draws in FP64 and converts each particle

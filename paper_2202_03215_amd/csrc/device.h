@@ -50,9 +50,8 @@ struct Counters {
     // bounded column with an external circuit and cathode emission (section V)
     double V;            // anode potential of the next field solve [V]
     double J;            // conduction current density of the last step [A/m^2]
-    int64_t vsum_e;      // electrons' sum of v_x (2^-20 m/s units) of the current step
-    int64_t vsum_ia;     // ions' sum of v_x accumulated by the current ion step
-    int64_t vsum_i;      // ions' sum of v_x of the last ion step (held between ion steps)
+    int64_t pad2[2];
+    int64_t vsum_i;      // ions' sum of v_x (2^-20 m/s units) of the last ion step (held)
     double carry;        // fractional emitted electrons carried to the next step
     int64_t pad1[2];
 };
@@ -110,6 +109,7 @@ struct Params {
     double circ_R;                  // series resistance [ohm m^2]
     double circ_a;                  // R eps0 / (L dt)
     double circ_jf;                 // e W / L per 2^-20 m/s: current density of one velocity unit
+    int64_t* csum;                  // v_x sums of the step: 64 electron slots, 64 ion slots
     // FP32 path: velocity scales (m/s per cell/step) and field scales
     double u2v_e, u2v_i;            // dx/dt, dx/dt_i
     double efs_e, efs_i;            // q dt^2/(m dx), q dt_i^2/(M dx)

@@ -129,13 +129,17 @@ __device__ __forceinline__ int64_t wave_append(bool flag, int64_t* counter)
 
 // Conduction-current sums of the external circuit (section V): v_x of the
 // particles alive after their push, truncated to 2^-20 m/s units, so that
-// the sum does not depend on the order of the atomics.
+// the sum does not depend on the order of the atomics.  Each lane sums its
+// particles over the chunk, each wave adds its total to one of kCurSlots
+// slots (spread so that waves do not queue on one address); the finish
+// kernel adds the slots up.
+constexpr int kCurSlots = 64;
 __device__ __forceinline__ int64_t vunits(double v) { return int64_t(v * 1048576.0); }
-__device__ __forceinline__ void add_current(int64_t* sum, bool alive, double vx)
+__device__ __forceinline__ void add_current(int64_t* slots, int64_t lane_sum)
 {
-    const uint64_t q = alive ? uint64_t(vunits(vx)) : 0ull;
-    const uint64_t t = __ockl_wfred_add_u64(q);
-    if (lane_id() == 0 && t != 0ull) atomicAdd((unsigned long long*)sum, (unsigned long long)t);
+    const uint64_t t = __ockl_wfred_add_u64(uint64_t(lane_sum));
+    const int slot = (int(blockIdx.x) * (kAdvBlock / 64) + int(threadIdx.x >> 6)) & (kCurSlots - 1);
+    if (lane_id() == 0 && t != 0ull) atomicAdd((unsigned long long*)&slots[slot], (unsigned long long)t);
 }
 
 // contiguous chunk kb of nb equal (64-aligned) chunks of a particle array
@@ -466,6 +470,7 @@ __device__ __forceinline__ void push_e_chunk(const Params& P, const Soa& sp, int
             pid = ld32(sp.id, i);
         }
     }
+    int64_t cur = 0;   // this lane's v_x sum (external circuit)
     for (uint32_t i0 = uint32_t(beg); i0 < ue; i0 += kAdvBlock) {
         const uint32_t i = i0 + threadIdx.x;
         const bool act = i < ue;
@@ -530,9 +535,10 @@ __device__ __forceinline__ void push_e_chunk(const Params& P, const Soa& sp, int
                 }
             }
         }
-        if (P.circuit) add_current(&P.cnt->vsum_e, alive, vx);
+        if (P.circuit && alive) cur += vunits(vx);
         deposit_wave(P, win, wbase, rho, alive, jn, an);
     }
+    if (P.circuit) add_current(P.csum, cur);
     __syncthreads();
     for (int k = threadIdx.x; k < kWindow; k += kAdvBlock) {
         const unsigned long long v = win[k];
@@ -572,6 +578,7 @@ __device__ __forceinline__ void advance_i_chunk(const Params& P, const Soa& sp, 
     __syncthreads();
     const double* __restrict__ E = P.E;
 
+    int64_t cur = 0;   // this lane's v_x sum (external circuit)
     for (int64_t i0 = beg; i0 < end; i0 += kAdvBlock) {
         const int64_t i = i0 + threadIdx.x;
         const bool act = i < end;
@@ -633,9 +640,10 @@ __device__ __forceinline__ void advance_i_chunk(const Params& P, const Soa& sp, 
             if (hp < P.max_holes) P.holes[kIon][hp] = uint32_t(i);
             else set_err(P, kErrLosses);
         }
-        if (P.circuit) add_current(&P.cnt->vsum_ia, alive, vpush);
+        if (P.circuit && alive) cur += vunits(vpush);
         deposit_wave(P, win, wbase, rho, alive, jn, an);
     }
+    if (P.circuit) add_current(P.csum + kCurSlots, cur);
     __syncthreads();
     for (int k = threadIdx.x; k < kWindow; k += kAdvBlock) {
         const unsigned long long v = win[k];
@@ -723,6 +731,7 @@ __device__ __forceinline__ void push_e_chunk(const Params& P, const Soa32& sp, i
             pid = ld32(sp.id, i);
         }
     }
+    int64_t cur = 0;   // this lane's v_x sum (external circuit)
     for (uint32_t i0 = uint32_t(beg); i0 < ue; i0 += kAdvBlock) {
         const uint32_t i = i0 + threadIdx.x;
         const bool act = i < ue;
@@ -783,9 +792,10 @@ __device__ __forceinline__ void push_e_chunk(const Params& P, const Soa32& sp, i
                 }
             }
         }
-        if (P.circuit) add_current(&P.cnt->vsum_e, alive, double(u) * P.u2v_e);
+        if (P.circuit && alive) cur += vunits(double(u) * P.u2v_e);
         deposit_wave(P, win, wbase, rho, alive, jn, an);
     }
+    if (P.circuit) add_current(P.csum, cur);
     __syncthreads();
     for (int k = threadIdx.x; k < kWindow; k += kAdvBlock) {
         const unsigned long long v = win[k];
@@ -816,6 +826,7 @@ __device__ __forceinline__ void advance_i_chunk(const Params& P, const Soa32& sp
     for (int k = threadIdx.x; k < kWindow; k += kAdvBlock) win[k] = 0ull;
     const int wbase = sp.cell[beg] - kHalo;
     __syncthreads();
+    int64_t cur = 0;   // this lane's v_x sum (external circuit)
     for (int64_t i0 = beg; i0 < end; i0 += kAdvBlock) {
         const int64_t i = i0 + threadIdx.x;
         const bool act = i < end;
@@ -873,9 +884,10 @@ __device__ __forceinline__ void advance_i_chunk(const Params& P, const Soa32& sp
             if (hp < P.max_holes) P.holes[kIon][hp] = uint32_t(i);
             else set_err(P, kErrLosses);
         }
-        if (P.circuit) add_current(&P.cnt->vsum_ia, alive, double(upush) * P.u2v_i);
+        if (P.circuit && alive) cur += vunits(double(upush) * P.u2v_i);
         deposit_wave(P, win, wbase, rho, alive, jn, an);
     }
+    if (P.circuit) add_current(P.csum + kCurSlots, cur);
     __syncthreads();
     for (int k = threadIdx.x; k < kWindow; k += kAdvBlock) {
         const unsigned long long v = win[k];
@@ -1384,9 +1396,22 @@ __device__ __forceinline__ void finish_column(const Params& P, const St& se, con
     //    from their last subcycle step) and the displacement current of the
     //    gap, backward Euler: V' (1 + a) = V_source + R J + a V, a = R eps0/(L dt)
     double Vf = P.V, Jc = 0.0;
+    int64_t vi = 0;
     if (P.circuit) {
-        const int64_t vi = step_in % P.ion_subcycle == 0 ? cnt->vsum_ia : cnt->vsum_i;
-        Jc = P.circ_jf * double(vi - cnt->vsum_e);
+        __shared__ int64_t sCur[2];
+        static_assert(kCurSlots == 64, "one slot per lane of wave 0");
+        if (tid < 64) {   // wave 0 adds the slots up
+            const uint64_t e = __ockl_wfred_add_u64(uint64_t(P.csum[tid]));
+            const uint64_t a = __ockl_wfred_add_u64(uint64_t(P.csum[kCurSlots + tid]));
+            if (tid == 0) {
+                sCur[0] = int64_t(e);
+                sCur[1] = int64_t(a);
+            }
+        }
+        __syncthreads();
+        const int64_t se = sCur[0], sa = sCur[1];
+        vi = step_in % P.ion_subcycle == 0 ? sa : cnt->vsum_i;
+        Jc = P.circ_jf * double(vi - se);
         Vf = (P.V + P.circ_R * Jc + P.circ_a * cnt->V) / (1.0 + P.circ_a);
     }
     // 1. field E^{n+1}.  An ionization adds an electron and an ion at the same
@@ -1596,11 +1621,7 @@ __device__ __forceinline__ void finish_column(const Params& P, const St& se, con
         if (P.circuit) {
             cnt->V = Vf;
             cnt->J = Jc;
-            cnt->vsum_e = 0;
-            if (step_in % P.ion_subcycle == 0) {
-                cnt->vsum_i = cnt->vsum_ia;
-                cnt->vsum_ia = 0;
-            }
+            if (step_in % P.ion_subcycle == 0) cnt->vsum_i = vi;
         }
         // ionization tallies of the balanced sink (an ion step consumed the
         // tally since the previous one)
@@ -1615,6 +1636,11 @@ __device__ __forceinline__ void finish_column(const Params& P, const St& se, con
     for (int j = tid; j < P.nn; j += T) {
         if (zero_a) zero_a[j] = 0;
         if (zero_b) zero_b[j] = 0;
+    }
+    // the current slots start the next step at zero (the ions' on their steps)
+    if (P.circuit && tid < kCurSlots) {
+        P.csum[tid] = 0;
+        if (step_in % P.ion_subcycle == 0) P.csum[kCurSlots + tid] = 0;
     }
 }
 

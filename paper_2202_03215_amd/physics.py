@@ -42,6 +42,36 @@ def run(cfg: dict, steps: int, every: int, eepf_from: int = 0, progress=None):
     return dict(times=np.array(times), ne=np.array(snaps), eepf=eepf, counts=np.array(counts))
 
 
+def bounded_run(cfg: dict, steps: int, every: int, snap_every: int = 10, progress=None):
+    """Free run of a bounded column with cathode emission and a series
+    resistor (section V).  Returns dict(times [s], V (anode potential), J
+    (conduction current density [A/m^2]), E_anode (field at the anode node
+    [V/m], the anode sheath), counts, ne [snapshots, cells] every
+    snap_every records)."""
+    from .column import Column
+    col = Column(cfg)
+    nc = int(cfg["n_cells"])
+    rec, snaps, counts = [], [], []
+    done = 0
+    while done < steps:
+        k = min(every, steps - done)
+        col.step(k)
+        done += k
+        c = col.counts()
+        E, _, _ = col.get_field()
+        rec.append((done * cfg["dt"], c["circuit"][0], c["J_cond"], float(E[-1])))
+        counts.append(c["n"])
+        if len(rec) % snap_every == 0:
+            mom = col.moments(nc).cpu().numpy()
+            snaps.append(A.split(mom, nc, nc)["ne"].astype(np.float64))
+        if progress is not None:
+            progress(done)
+    col.sync()
+    r = np.array(rec)
+    return dict(times=r[:, 0], V=r[:, 1], J=r[:, 2], E_anode=r[:, 3], counts=np.array(counts),
+                ne=np.array(snaps))
+
+
 def striation_summary(res: dict, cfg: dict, t_from: float) -> dict:
     """Dominant mode, wavelength, phase velocity and potential drop per
     striation of the snapshots after t_from, plus the modulation depth."""
