@@ -37,7 +37,7 @@ HBM_PEAK_GBS = 8000.0   # MI355X HBM3E, GB/s
 # (KiB) and the counter calibration against a 512 MiB device copy (fetch x2.00,
 # write x1.00); profiles/push_counters_column_20cm_50cm.md.  Valid for the
 # kernel they were taken on only.
-PUSH_COUNTERS_KIB = {"column_20cm": (6804.0, 6904.0), "column_50cm": (79427.0, 82390.0)}
+PUSH_COUNTERS_KIB = {"column_20cm": (6803.0, 6905.0), "column_50cm": (79323.0, 82399.0)}
 COUNTER_CAL = (2.00, 1.00)
 
 WORKLOADS = {
