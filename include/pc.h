@@ -177,7 +177,8 @@ pc_status pc_get_state(pc_handle h, int32_t species, double* x, double* vx, doub
                        double* vz, uint32_t* id, int64_t cap);
 
 /* Replace a species' particles with n caller device arrays (async).  Clears
- * a poisoned handle.  Positions must lie in [0, L). */
+ * a poisoned handle.  Positions must lie in [0, L).  For the ions, the charge
+ * held between ion steps is redeposited from the new particles. */
 pc_status pc_set_state(pc_handle h, int32_t species, int64_t n, const double* x,
                        const double* vx, const double* vy, const double* vz,
                        const uint32_t* id);

@@ -774,6 +774,15 @@ pc_status pc_set_state(pc_handle h, int32_t species, int64_t n, const double* x,
         HIPCHK(pclaunch::deposit(h->P, q.x, n, scratch, h->st));
         HIPCHK(pclaunch::fill_i64(scratch, h->d.nn, 0, h->st));
     }
+    // the ions' charge is held between ion steps: it is the new ions' from now on
+    if (species == 1) {
+        int64_t* held = h->rho[1][h->ri_cur];
+        HIPCHK(pclaunch::fill_i64(held, h->d.nn, 0, h->st));
+        if (n > 0) {
+            if (h->fp32) HIPCHK(pclaunch::deposit(h->P, h->buf32[1][h->cur[1]], n, held, h->st));
+            else HIPCHK(pclaunch::deposit(h->P, q.x, n, held, h->st));
+        }
+    }
     if (n > 0) {
         if ((s = read_counters(h)) != PC_OK) return s;
         if (h->host_cnt.err) {

@@ -234,6 +234,41 @@ def test_step_parity_hot_cathode_and_circuit(torch_cuda):
     assert abs(seen[-1][1] - cfg["V"]) > 0.01             # the resistor moved the anode potential
 
 
+@pytest.mark.parametrize("bc", ["bounded", "periodic"])
+def test_empty_column_steps(torch_cuda, bc):
+    # no particles at all: every kernel sees empty chunks; the field is the
+    # Laplace field of the gap (bounded: the anode relaxes through the series
+    # resistor as an RC circuit, V_n = U + (V_0 - U) (a / (1 + a))^n)
+    cfg = W.tiny(bc, n_cells=400, L=0.04, V=40.0, ppc=2,
+                 **({"circuit_R": 2.0} if bc == "bounded" else {}))
+    col = _column(cfg)
+    orc = Oracle(cfg, init=False)
+    z = np.zeros(0)
+    zi = np.zeros(0, dtype=np.uint32)
+    for s in (ELECTRON, ION):
+        col.set_state(s, z, z, z, z, zi)
+        orc.set_state(s, z, z, z, z, zi)
+    V0 = 5.0 if bc == "bounded" else cfg["V"]
+    col.set_circuit(V0, 0, 0.0)
+    orc.set_circuit(V0, 0, 0.0)
+    a = cfg.get("circuit_R", 0.0) * 8.8541878128e-12 / (cfg["L"] * cfg["dt"])
+    for n in range(1, 51):
+        col.step(1)
+        orc.step(1)
+        c = col.counts()
+        assert c["errors"] == 0 and c["n"] == (0, 0)
+        Eg = col.get_field()[0].cpu().numpy()
+        Eo = orc.field()[0]
+        assert np.abs(Eg - Eo).max() <= 1e-12 * np.abs(Eo).max()
+        if bc == "bounded":
+            V = c["circuit"][0]
+            expect = cfg["V"] + (V0 - cfg["V"]) * (a / (1.0 + a)) ** n
+            assert abs(V - expect) <= 1e-12 * cfg["V"] and abs(V - orc.circuit()["V_anode"]) <= 1e-13 * cfg["V"]
+            assert np.abs(Eg[:col.nn] + V / cfg["L"]).max() <= 1e-12 * V / cfg["L"]
+        else:
+            assert np.abs(Eg[:col.nn] + cfg["V"] / cfg["L"]).max() <= 1e-12 * cfg["V"] / cfg["L"]
+
+
 def test_step_parity_long_loss_and_birth_lists(torch_cuda):
     # more than 2048 losses and ionizations in one step: the finish kernel
     # takes its global-scratch paths instead of the LDS lists
