@@ -126,7 +126,7 @@ def measure(cfg: dict, args, tag: str) -> dict:
           file=sys.stderr, flush=True)
     del col
     torch.cuda.empty_cache()
-    return {"value": value, "elapsed": elapsed, "ne": ne_avg, "ni": ni_avg,
+    return {"value": value, "elapsed": elapsed, "ne": ne_avg, "ni": ni_avg, "ion_steps": ion_steps,
             "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                          "frac": achieved / HBM_PEAK_GBS, "traffic": None,
                          "kernel": "k_push_e<false, Soa32>" if fp32 else "k_push_e<false, Soa>",
@@ -134,6 +134,37 @@ def measure(cfg: dict, args, tag: str) -> dict:
                          "bytes_per_launch": bytes_per_launch,
                          "window": "eager timed window of the same length after the graph window",
                          "ms_per_step_eager": (t3 - t2) * 1e3 / args.steps}}
+
+
+def measure_sequential(cfgs: list, steps: int = 160, warmup: int = 160) -> dict:
+    """The same columns as plain FP64 single columns, one after the other
+    (each graph-replayed on its own): the baseline the batched FP32 launch
+    is compared with."""
+    import torch
+    from paper_2202_03215_amd.column import Column
+    work = 0.0
+    elapsed = 0.0
+    for cfg in cfgs:
+        c = W.with_(cfg, precision="fp64")
+        col = Column(c)
+        col.step(warmup)
+        col.sync()
+        n0 = col.counts()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        col.step(steps)
+        torch.cuda.synchronize()
+        elapsed += time.perf_counter() - t0
+        n1 = col.counts()
+        col.sync()
+        S = int(c["ion_subcycle"])
+        ion_steps = sum(1 for k in range(n0["step"], n0["step"] + steps) if k % S == 0)
+        work += 0.5 * (n0["n"][0] + n1["n"][0]) * steps + 0.5 * (n0["n"][1] + n1["n"][1]) * ion_steps
+        del col
+    torch.cuda.empty_cache()
+    print(f"[bench] sequential fp64 columns: {len(cfgs)} x {steps} steps in {elapsed:.3f} s",
+          file=sys.stderr, flush=True)
+    return {"value": work / elapsed, "steps_per_column": steps, "dtype": "f64"}
 
 
 def measure_batch(cfgs: list, args) -> dict:
@@ -310,6 +341,8 @@ def main() -> int:
                    "electrons": int(ne_avg), "ions": int(ni_avg), "dt": cfg["dt"],
                    "ion_subcycle": S, "sort_interval": cfg["sort_interval"]},
         "roofline": r64["roofline"],
+        "electron_steps_per_s": ne_avg * args.steps / elapsed,
+        "ion_steps_per_s": ni_avg * r64["ion_steps"] / elapsed,
     }
     if args.workload in PUSH_COUNTERS_KIB:
         f, w = PUSH_COUNTERS_KIB[args.workload]
@@ -332,10 +365,13 @@ def main() -> int:
     if not args.no_batch:
         cfgs = W.argon_scan(args.batch_columns)
         rb = measure_batch(cfgs, args)
+        rs = measure_sequential(cfgs)
         out["batched"] = {"workload": f"argon_scan_{args.batch_columns}", "columns": len(cfgs),
                           "cells": [min(c["n_cells"] for c in cfgs), max(c["n_cells"] for c in cfgs)],
                           "dtype": "f32 particles, f64 field", **rb,
-                          "speedup_vs_plain_fp64": rb["value"] / value}
+                          "speedup_vs_plain_fp64": rb["value"] / value,
+                          "sequential_fp64_columns": rs,
+                          "speedup_vs_sequential_fp64_columns": rb["value"] / rs["value"]}
     if not args.no_fluid:
         out["fluid"] = measure_fluid(args, elapsed * 1e3 / args.steps, float(cfg["dt"]))
     if not args.no_cpu:
