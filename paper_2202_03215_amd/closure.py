@@ -166,3 +166,32 @@ def predict(net, X, norm):
     xn, _ = normalise(X, None, norm)
     y = net.forward(torch.from_numpy(xn)).cpu().numpy().astype(np.float64)
     return y * norm[10:12] + norm[12:14]
+
+
+def fluid_striations(table, T_min: float, T_step: float, Ngas: float, E0: float, L: float, n_cells: int,
+                     dt: float, steps: int, every: int = 100, net=None, norm=None, muiN: float = 4.0e21,
+                     seed: int = 1):
+    """Free run of GPU fluid columns (two identical columns) at the mean field
+    E0 from the homogeneous steady state of the table (nu_w = nu_i(T0)) with a
+    1e-3 density noise, with the table closure or, given (net, norm), the
+    learned one.  Returns (times, dominant mode, its modulation) of column 0
+    every `every` steps: lambda = L / mode, to set against the PIC column."""
+    from . import stability as S
+    from .fluid import FluidBatch
+    T0 = S.temperature_for_field(table, T_min, T_step, Ngas, E0)
+    nu_w = Ngas * S._row(np.asarray(table, dtype=np.float64), T_min, T_step, T0)[0][4]
+    fb = FluidBatch([dict(L=L, Ngas=Ngas, E0=E0, nu_w=nu_w, muiN=muiN)] * 2, n_cells, dt, table, T_min, T_step)
+    if net is not None:
+        fb.set_closure(net, norm)
+    rng = np.random.default_rng(seed)
+    n0 = 1e15 * (1.0 + 1e-3 * rng.normal(size=(2, n_cells)))
+    fb.set_state(n0, 1.5 * n0 * T0)
+    out = []
+    for s in range(steps // every):
+        fb.step(every)
+        n, _ = (t.cpu().numpy().astype(np.float64) for t in fb.get_state())
+        sp = np.abs(np.fft.rfft(n[0] - n[0].mean()))
+        m = int(np.argmax(sp[1:]) + 1)
+        out.append(((s + 1) * every * dt, m, 2.0 * sp[m] / n_cells / n[0].mean()))
+    a = np.array(out)
+    return a[:, 0], a[:, 1].astype(int), a[:, 2]
