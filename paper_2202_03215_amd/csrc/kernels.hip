@@ -1068,14 +1068,23 @@ __device__ __forceinline__ FieldLoads field_load(const Params& P, const int64_t*
 __device__ void field_solve(const Params& P, const FieldLoads& fl, double* __restrict__ E,
                             double* __restrict__ phi, bool ghost, bool scaled, double V)
 {
-    __shared__ int64_t shi[kOneBlock / 64 + 1];
+    // One barrier: each wave posts its charge total and its share of
+    // S = sum_{j<nc} T_j = sum_{k=1..nc-1} (nc - k) Q_k; every thread then
+    // reads the (<= 16) wave entries itself, in wave order, for its scan
+    // offset, the totals and S.  The left neighbour's last half-cell field is
+    // E_{1/2} + fpc T_{j0-1}, and T_{j0-1} is the thread's own scan offset, so
+    // no field value is exchanged between threads.
+    __shared__ int64_t shq[kOneBlock / 64];
+    __shared__ double shw[kOneBlock / 64];
     __shared__ double shd[kOneBlock / 64 + 1];
-    __shared__ double edge[kOneBlock + 1];
+    __shared__ int64_t q0s;
     const int nn = P.nn, nc = P.nc;
     const int seg = (nn + blockDim.x - 1) / blockDim.x;
     const int j0 = threadIdx.x * seg;
+    const int wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
     int64_t q[kMaxSeg];
     int64_t loc = 0;
+    double wsum = 0.0;
 #pragma unroll
     for (int k = 0; k < kMaxSeg; ++k) {
         const int j = j0 + k;
@@ -1083,10 +1092,24 @@ __device__ void field_solve(const Params& P, const FieldLoads& fl, double* __res
         if (k < seg && j < nn) {
             q[k] = fl.ri[k] - fl.re[k];
             if (j >= 1) loc += q[k];
+            if (j >= 1 && j < nc) wsum += double(q[k]) * double(nc - j);
         }
     }
-    int64_t qtot_excl0;
-    const int64_t off = block_excl_scan<int64_t>(loc, shi, qtot_excl0);
+    const int64_t incl = wave_incl_scan(loc);
+    const double wred = __ockl_wfred_add_f64(wsum);
+    if (lane_id() == 63) shq[wid] = incl;
+    if (lane_id() == 0) shw[wid] = wred;
+    if (threadIdx.x == 0) q0s = q[0];
+    __syncthreads();
+    int64_t off = incl - loc, qtot_excl0 = 0;
+    double S = 0.0;
+    for (int w = 0; w < nw; ++w) {
+        const int64_t t = shq[w];
+        if (w < wid) off += t;
+        qtot_excl0 += t;
+        S += shw[w];
+    }
+    const int64_t qall = qtot_excl0 + q0s;   // periodic total charge
     // T_j for own nodes (T_0 = 0; Q_0 excluded)
     int64_t T[kMaxSeg];
     {
@@ -1098,43 +1121,31 @@ __device__ void field_solve(const Params& P, const FieldLoads& fl, double* __res
             T[k] = run;
         }
     }
-    __shared__ int64_t q0s;
-    if (threadIdx.x == 0) q0s = q[0];
-    __syncthreads();
-    const int64_t qall = qtot_excl0 + q0s;   // periodic total charge
-    double Tp[kMaxSeg];
-    double lsum = 0.0;
+    // periodic: T_j - j Q / nc (mean charge removed), whose sum over j < nc
+    // is S - Q (nc - 1) / 2
     const double qbar = double(qall) / double(nc);
-#pragma unroll
-    for (int k = 0; k < kMaxSeg; ++k) {
-        const int j = j0 + k;
-        Tp[k] = 0.0;
-        if (k < seg && j < nc) {
-            Tp[k] = P.periodic ? double(T[k]) - double(j) * qbar : double(T[k]);
-            lsum += Tp[k];
-        }
-    }
-    const double st = block_sum(lsum, shd);
+    const double st = P.periodic ? S - 0.5 * double(qall) * double(nc - 1) : S;
     const double eh0 = P.periodic ? -(P.fpc * (st / double(nc))) : -(V / P.L) - P.fpc * (st / double(nc));
     double Eh[kMaxSeg];
 #pragma unroll
-    for (int k = 0; k < kMaxSeg; ++k) Eh[k] = eh0 + P.fpc * Tp[k];
-    // last half-cell field of each thread, for the left neighbour of node j0
-    const int jl = (j0 + seg - 1 < nc - 1) ? j0 + seg - 1 : nc - 1;
-    if (j0 < nc) edge[threadIdx.x + 1] = Eh[jl - j0];
-    __syncthreads();
-    // left neighbour of node 0: the last cell's half-cell field (periodic)
-    const double edge0 = P.periodic ? edge[(nc - 1) / seg + 1] : 0.0;
+    for (int k = 0; k < kMaxSeg; ++k) {
+        const int j = j0 + k;
+        Eh[k] = eh0 + P.fpc * (P.periodic ? double(T[k]) - double(j) * qbar : double(T[k]));
+    }
+    // left neighbour of node j0 (> 0): half-cell j0 - 1, T_{j0-1} = off; of
+    // node 0 (periodic): the last cell's, T_{nc-1} = the total without Q_0
+    const double left0 = j0 == 0
+        ? (P.periodic ? eh0 + P.fpc * (double(qtot_excl0) - double(nc - 1) * qbar) : 0.0)
+        : eh0 + P.fpc * (P.periodic ? double(off) - double(j0 - 1) * qbar : double(off));
     bool bad = false;
 #pragma unroll
     for (int k = 0; k < kMaxSeg; ++k) {
         const int j = j0 + k;
         if (k >= seg || j >= nn) break;
-        const double left = k == 0 ? (threadIdx.x == 0 ? edge0 : edge[threadIdx.x]) : Eh[k - 1];
+        const double left = k == 0 ? left0 : Eh[k - 1];
         double e;
         if (P.periodic) {
-            const double lft = j == 0 ? edge0 : left;
-            e = -P.E0 + 0.5 * (lft + Eh[k]);
+            e = -P.E0 + 0.5 * (left + Eh[k]);
         } else if (j == 0) {
             e = Eh[0] - P.fpc * double(q[0]);
         } else if (j == nc) {
@@ -1430,8 +1441,8 @@ __device__ __forceinline__ void finish_column(const Params& P, const St& se, con
                 P.Ef_i[j] = float(e0 * P.efs_i);
             }
         }
+        __syncthreads();   // (the solve's own barrier orders the LDS clears above)
     }
-    __syncthreads();
     const uint32_t step = uint32_t(step_in);
 
     // 2. births: parent update, products' charge; product velocities kept in
