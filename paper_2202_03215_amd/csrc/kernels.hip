@@ -1065,7 +1065,35 @@ __device__ __forceinline__ FieldLoads field_load(const Params& P, const int64_t*
     return fl;
 }
 
-__device__ void field_solve(const Params& P, const FieldLoads& fl, double* __restrict__ E,
+// The thread's own node charges Q_j and partial sums, taken from the loads
+// as soon as they arrive (a caller that issues more loads after these does
+// not make the solve wait for those).
+struct FieldPre {
+    int64_t q[kMaxSeg];
+    int64_t loc;     // sum of own Q_j, j >= 1
+    double wsum;     // sum of own (nc - j) Q_j, 1 <= j < nc
+};
+__device__ __forceinline__ FieldPre field_prepare(const Params& P, const FieldLoads& fl)
+{
+    FieldPre f;
+    const int nn = P.nn, nc = P.nc;
+    const int seg = (nn + blockDim.x - 1) / blockDim.x;
+    const int j0 = threadIdx.x * seg;
+    f.loc = 0;
+    f.wsum = 0.0;
+#pragma unroll
+    for (int k = 0; k < kMaxSeg; ++k) {
+        const int j = j0 + k;
+        const bool own = k < seg && j < nn;
+        const int64_t qk = own ? fl.ri[k] - fl.re[k] : 0;
+        f.q[k] = qk;
+        f.loc += j >= 1 ? qk : 0;
+        f.wsum += (j >= 1 && j < nc) ? double(qk) * double(nc - j) : 0.0;
+    }
+    return f;
+}
+
+__device__ void field_solve(const Params& P, const FieldPre& fp, double* __restrict__ E,
                             double* __restrict__ phi, bool ghost, bool scaled, double V)
 {
     // One barrier: each wave posts its charge total and its share of
@@ -1082,19 +1110,9 @@ __device__ void field_solve(const Params& P, const FieldLoads& fl, double* __res
     const int seg = (nn + blockDim.x - 1) / blockDim.x;
     const int j0 = threadIdx.x * seg;
     const int wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
-    int64_t q[kMaxSeg];
-    int64_t loc = 0;
-    double wsum = 0.0;
-#pragma unroll
-    for (int k = 0; k < kMaxSeg; ++k) {
-        const int j = j0 + k;
-        q[k] = 0;
-        if (k < seg && j < nn) {
-            q[k] = fl.ri[k] - fl.re[k];
-            if (j >= 1) loc += q[k];
-            if (j >= 1 && j < nc) wsum += double(q[k]) * double(nc - j);
-        }
-    }
+    const int64_t* q = fp.q;
+    const int64_t loc = fp.loc;
+    const double wsum = fp.wsum;
     const int64_t incl = wave_incl_scan(loc);
     const double wred = __ockl_wfred_add_f64(wsum);
     if (lane_id() == 63) shq[wid] = incl;
@@ -1189,7 +1207,8 @@ __global__ __launch_bounds__(kOneBlock) void k_field(Params P, const int64_t* rh
                                                      double* E, double* phi, int ghost)
 {
     if (P.poisson || phi != nullptr || !ghost) {
-        field_solve(P, field_load(P, rho_e, rho_i), E, phi, ghost != 0, false, P.circuit ? P.cnt->V : P.V);
+        field_solve(P, field_prepare(P, field_load(P, rho_e, rho_i)), E, phi, ghost != 0, false,
+                    P.circuit ? P.cnt->V : P.V);
     } else {
         const double e0 = P.periodic ? -P.E0 : -((P.circuit ? P.cnt->V : P.V) / P.L);
         for (int j = threadIdx.x; j <= P.nn; j += blockDim.x) E[j] = e0;
@@ -1340,17 +1359,18 @@ __device__ __forceinline__ void finish_column(const Params& P, const St& se, con
     __shared__ unsigned int sC[4];
     const int tid = threadIdx.x;
     const int T = blockDim.x;
-    // the charge loads of the field solve go first: they depend on nothing
-    // else, and the loads below wait for the counters
-    FieldLoads fl;
-    if (P.poisson && !P.pair) fl = field_load(P, rho_e, rho_i);
+    // the step's counters (the same words for every thread) and the charge
+    // loads of the field solve go first, together: they depend on nothing
+    // else.  The charges are reduced to the thread's partial sums before the
+    // loads that wait for the counters are issued.
     Counters* cnt = P.cnt;
-    // the step's counters (the same words for every thread)
     const int64_t n_in[2] = {cnt->n[0], cnt->n[1]};
     const int64_t nh_in[2] = {cnt->nh[0], cnt->nh[1]};
     const int64_t id_in[2] = {cnt->next_id[0], cnt->next_id[1]};
     const int64_t nb_in = cnt->nb;
     const int64_t step_in = cnt->step;
+    FieldPre fp;
+    if (P.poisson && !P.pair) fp = field_prepare(P, field_load(P, rho_e, rho_i));
     int64_t nb = nb_in < P.max_births ? nb_in : P.max_births;
     int64_t nh[2], Np[2];
     bool lds[2];
@@ -1400,7 +1420,7 @@ __device__ __forceinline__ void finish_column(const Params& P, const St& se, con
     //    are empty in this mode, so their LDS arrays hold the victims)
     if (P.pair) {
         pair_victims(P, se, si, rho_e, rho_i, nb, uint32_t(step_in), id_in, sL1, sL2);
-        if (P.poisson) fl = field_load(P, rho_e, rho_i);
+        if (P.poisson) fp = field_prepare(P, field_load(P, rho_e, rho_i));
     }
     // 0b. external circuit (section V): the anode potential of this solve from
     //    the step's conduction current (particles' v_x after their push; ions
@@ -1431,7 +1451,7 @@ __device__ __forceinline__ void finish_column(const Params& P, const St& se, con
     //    advance kernels and runs first.
     //    FP32 particles also get the field scaled to cells per step^2.
     if (P.poisson) {
-        field_solve(P, fl, P.E, nullptr, true, P.Ef_e != nullptr, Vf);
+        field_solve(P, fp, P.E, nullptr, true, P.Ef_e != nullptr, Vf);
     } else {
         const double e0 = P.periodic ? -P.E0 : -(Vf / P.L);
         for (int j = tid; j <= P.nn; j += T) {
