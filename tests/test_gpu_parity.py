@@ -66,7 +66,7 @@ def test_deposit_bitwise(torch_cuda, bc, n):
 
 # -------------------------------------------------------------- field solve
 @pytest.mark.parametrize("bc", ["bounded", "periodic"])
-@pytest.mark.parametrize("nc", [37, 400, 2000, 5000, 8000])
+@pytest.mark.parametrize("nc", [37, 400, 2000, 5000, 8000, 8191])   # 8191: 8192 bounded nodes, the maximum
 def test_field_solve(torch_cuda, bc, nc):
     torch = torch_cuda
     L = nc * 1e-4
