@@ -86,6 +86,31 @@ def test_field_solve(torch_cuda, bc, nc):
 
 
 @pytest.mark.parametrize("bc", ["bounded", "periodic"])
+@pytest.mark.parametrize("one_signed", [False, True])
+def test_field_solve_large_charges(torch_cuda, bc, one_signed):
+    # node charges up to 2^45 units on the 8192-node maximum: the potential
+    # constant's weighted sum (n_c - k) Q_k reaches 2^58 per term, beyond the
+    # 53-bit mantissa, and the integer prefix sums reach 2^58; one-signed: a
+    # net charge of 2^58 units (a column of electrons only)
+    torch = torch_cuda
+    nc = 8191
+    L = nc * 1e-4
+    cfg = W.tiny(bc=bc, n_cells=nc, L=L, V=L * 1000.0, ppc=2)
+    col = _column(cfg)
+    orc = Oracle(cfg, init=False)
+    re, ri = W.charge_profile(col.nn, seed=5, scale=1 << 45)
+    if one_signed:
+        ri = np.zeros_like(ri)
+    phi_g, E_g = col.solve_field(torch.from_numpy(re), torch.from_numpy(ri))
+    phi_o, E_o = orc.solve_field(re, ri)
+    E_g = E_g.cpu().numpy()
+    phi_g = phi_g.cpu().numpy()
+    assert np.abs(E_g - E_o).max() <= 1e-12 * np.abs(E_o).max()
+    scale = max(np.abs(phi_o).max(), abs(cfg["V"]))
+    assert np.abs(phi_g - phi_o).max() <= 1e-12 * scale
+
+
+@pytest.mark.parametrize("bc", ["bounded", "periodic"])
 def test_field_zero_charge(torch_cuda, bc):
     torch = torch_cuda
     cfg = W.tiny(bc=bc, n_cells=400, L=0.04, V=40.0, ppc=2)
