@@ -310,7 +310,7 @@ def main() -> int:
                     help="also run a plain device copy of this many MiB (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on exactly one GPU (no sharding or "
+        print(json.dumps({"error": "the engine runs a column on exactly one GPU (no sharding or "
                                    "collectives); run with --gpus 1"}))
         return 2
 
