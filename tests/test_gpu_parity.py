@@ -183,6 +183,25 @@ def _run_shared_state(torch, cfg, steps, min_events=None, setup=None, check=None
     return tot
 
 
+def test_step_parity_column_20cm_full_size(torch_cuda):
+    # the bench's workload in the bench's launch grid (400k + 400k particles,
+    # 2000 cells, one initial particle per thread): 38 steps on the GPU alone
+    # (births, losses, the sort and ion step at 20), then steps 38-40 from the
+    # shared state (the sort after step 39, the ion step 40), every particle
+    # compared
+    cfg = W.column_20cm()
+    _run_shared_state(torch_cuda, cfg, steps=3, setup=lambda col: col.step(38), min_events={1: 1000, 7: 10000})
+
+
+def test_step_parity_column_50cm_full_size(torch_cuda):
+    # the large column (5M + 5M particles, 5000 cells, 4096 blocks of about
+    # five tiles, the finish with 768 threads): steps 19 and 20 from the
+    # shared state after 19 steps alone (step 19 ends with the sort, step 20
+    # is an ion step)
+    cfg = W.column_50cm()
+    _run_shared_state(torch_cuda, cfg, steps=2, setup=lambda col: col.step(19), min_events={1: 1000, 7: 50000})
+
+
 def test_step_parity_small_bounded(torch_cuda):
     # neon, 4 cm, 400 cells, 50 per cell, grounded cathode / 40 V anode
     _run_shared_state(torch_cuda, W.small_bounded(), steps=60, min_events={1: 50, 5: 20})
