@@ -92,6 +92,27 @@ def test_batch_columns_equal_single_columns(torch_cuda, precision):
     assert b.column(0).counts()["next_id"][0] > cfgs[0]["ppc"] * cfgs[0]["n_cells"]
 
 
+def test_full_size_scan_members_equal_single_columns(torch_cuda):
+    # the bench's batched workload: the 64-column argon scan (1000-8000
+    # cells, 100-400 per cell, 82M + 82M FP32 particles) with the bench's
+    # tuned setting (4096-particle chunks, sort every 80 steps); after one
+    # graph period (160 steps) the smallest, the largest and the first column
+    # are bitwise the same column stepped alone
+    cfgs = W.argon_scan(64)
+    b = _batch(cfgs)
+    b.set_tuning(4096, 80)
+    steps = 160
+    b.step(steps)
+    b.sync()
+    sizes = [c["n_cells"] * c["ppc"] for c in cfgs]
+    for k in sorted({int(np.argmin(sizes)), int(np.argmax(sizes)), 0}):
+        cfg = W.with_(cfgs[k], sort_interval=80)
+        got = _snapshot(b.column(k))
+        assert got[0]["step"] == steps
+        _same(got, _alone(cfg, steps), f"column {k}")
+    del b
+
+
 def test_batch_tuning_and_graphs_do_not_change_results(torch_cuda):
     cfgs = _mixed("fp64", sort_interval=4)
     steps = 200
