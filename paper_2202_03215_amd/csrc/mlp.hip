@@ -27,6 +27,7 @@ namespace pcmlp {
 
 typedef __bf16 bf16;
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 
 constexpr int kIn = 5, kH = 64, kOut = 2;
@@ -42,7 +43,7 @@ static_assert(kParams == PC_MLP_PARAMS, "parameter count");
 // operand layouts: forward B operands are W^T rows (8 consecutive inputs of
 // one output unit); backward B operands are W rows (8 consecutive outputs of
 // one input unit); K and N are padded with zeros.
-struct PackedFwd {
+struct alignas(16) PackedFwd {
     bf16 w1t[kH][32];   // [out][in, padded 5 -> 32]
     bf16 w2t[kH][kH];
     bf16 w3t[kH][kH];
@@ -75,22 +76,21 @@ __device__ __forceinline__ void stage_params(T& s, const Packed* __restrict__ g)
 }
 
 // One dense layer for a 16-sample tile held row-major in LDS (act[16][K]):
-// out[s][u] = sum_k act[s][k] W[k][u] + b[u] for the 4 N-tiles of 64 units;
-// returns the 4 accumulator tiles.
+// out[s][u] = sum_k act[s][k] W[k][u] + b[u] for the 4 N-tiles of 64 units,
+// computed transposed (out^T = W^T act^T: the weights are the A operand, the
+// activations the B operand), so that lane l holds units nt 16 + 4(l/16) ..
+// + 3 of sample l % 16: four consecutive units of one row.
 template <int K>
 __device__ __forceinline__ void layer64(const bf16 (*act)[K], const bf16 (*wt)[K], const float* b, f32x4 acc[4])
 {
     const int l = lane();
 #pragma unroll
-    for (int nt = 0; nt < 4; ++nt) {
-        const float bias = b[nt * 16 + (l & 15)];
-        acc[nt] = f32x4{bias, bias, bias, bias};
-    }
+    for (int nt = 0; nt < 4; ++nt) acc[nt] = *reinterpret_cast<const f32x4*>(&b[nt * 16 + 4 * (l >> 4)]);
 #pragma unroll
     for (int kt = 0; kt < K / 32; ++kt) {
-        const bf16x8 a = ld8(&act[l & 15][kt * 32 + 8 * (l >> 4)]);
+        const bf16x8 xb = ld8(&act[l & 15][kt * 32 + 8 * (l >> 4)]);
 #pragma unroll
-        for (int nt = 0; nt < 4; ++nt) acc[nt] = mfma(a, ld8(&wt[nt * 16 + (l & 15)][kt * 32 + 8 * (l >> 4)]), acc[nt]);
+        for (int nt = 0; nt < 4; ++nt) acc[nt] = mfma(ld8(&wt[nt * 16 + (l & 15)][kt * 32 + 8 * (l >> 4)]), xb, acc[nt]);
     }
 }
 
@@ -106,21 +106,23 @@ __device__ __forceinline__ float tanh_bf(float x)
     return copysignf(r, x);
 }
 
-// tanh of the accumulators, rounded to BF16, into a row-major LDS tile
-// (and optionally to global memory, row-major [sample][64])
+// tanh of the accumulators (layer64's layout), rounded to BF16, into a
+// row-major LDS tile (and optionally to global memory, row-major
+// [sample][64]): four consecutive units per lane, one 8-byte store each
 __device__ __forceinline__ void tanh_store(const f32x4 acc[4], bf16 (*act)[kH], bf16* __restrict__ g, int64_t s0,
                                            int64_t n)
 {
     const int l = lane();
+    const int r = l & 15;
 #pragma unroll
-    for (int nt = 0; nt < 4; ++nt)
+    for (int nt = 0; nt < 4; ++nt) {
+        const int u = nt * 16 + 4 * (l >> 4);
+        bf16x4 h;
 #pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            const int r = 4 * (l >> 4) + i, u = nt * 16 + (l & 15);
-            const bf16 h = bf16(tanh_bf(acc[nt][i]));
-            act[r][u] = h;
-            if (g != nullptr && s0 + r < n) g[(s0 + r) * kH + u] = h;
-        }
+        for (int i = 0; i < 4; ++i) h[i] = bf16(tanh_bf(acc[nt][i]));
+        *reinterpret_cast<bf16x4*>(&act[r][u]) = h;
+        if (g != nullptr && s0 + r < n) *reinterpret_cast<bf16x4*>(&g[(s0 + r) * kH + u]) = h;
+    }
 }
 
 // input tile: 16 samples x 5 features -> BF16, padded to 32
@@ -135,7 +137,7 @@ __device__ __forceinline__ void load_x(const float* __restrict__ x, int64_t s0, 
     }
 }
 
-struct WaveLds {
+struct alignas(16) WaveLds {
     bf16 x[kTile][32];
     bf16 h1[kTile][kH];
     bf16 h2[kTile][kH];
@@ -174,6 +176,62 @@ __device__ __forceinline__ void forward_tile(const PackedFwd& P, WaveLds& w, con
     out[0] = o;
 }
 
+// Inference needs each activation only for the next layer: two ping-pong
+// tiles instead of three, no gradient tile (5 KB per wave, so that 16 waves
+// of 512-thread blocks fit a compute unit with the staged weights).
+constexpr int kFwdBlock = 512;   // 8 waves
+struct alignas(16) FwdLds {
+    bf16 x[kTile][32];
+    bf16 ha[kTile][kH];
+    bf16 hb[kTile][kH];
+};
+
+// The 16 x 5 inputs of a tile are 80 consecutive floats: lanes l and l + 64
+// (< 80) load one each, a tile ahead of its use; the tile's padding columns
+// 5..31 are zeroed once per wave and never written again.
+struct XFetch {
+    float v0, v1;
+};
+__device__ __forceinline__ XFetch fetch_x(const float* __restrict__ x, int64_t s0, int64_t n)
+{
+    const int l = lane();
+    const int64_t e = s0 * kIn, end = n * kIn;
+    XFetch f;
+    f.v0 = e + l < end ? x[e + l] : 0.0f;
+    f.v1 = (l < kTile * kIn - 64 && e + 64 + l < end) ? x[e + 64 + l] : 0.0f;
+    return f;
+}
+__device__ __forceinline__ void put_x(const XFetch& f, bf16 (*xs)[32])
+{
+    const int l = lane();
+    xs[l / kIn][l % kIn] = bf16(f.v0);
+    if (l < kTile * kIn - 64) xs[(64 + l) / kIn][(64 + l) % kIn] = bf16(f.v1);
+}
+
+__device__ __forceinline__ void forward_tile_inf(const PackedFwd& P, FwdLds& w, const XFetch& xf, int64_t s0,
+                                                 int64_t n, bf16* __restrict__ hidden, f32x4 out[1])
+{
+    f32x4 acc[4];
+    put_x(xf, w.x);
+    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "workgroup");
+    layer64<32>(w.x, P.w1t, P.b1, acc);
+    tanh_store(acc, w.ha, hidden, s0, n);
+    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "workgroup");
+    layer64<kH>(w.ha, P.w2t, P.b2, acc);
+    tanh_store(acc, w.hb, hidden ? hidden + n * kH : nullptr, s0, n);
+    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "workgroup");
+    layer64<kH>(w.hb, P.w3t, P.b3, acc);   // (the reads of ha above completed in order)
+    tanh_store(acc, w.ha, hidden ? hidden + 2 * n * kH : nullptr, s0, n);
+    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "workgroup");
+    const int l = lane();
+    const float bias = P.b4[l & 15];
+    f32x4 o = f32x4{bias, bias, bias, bias};
+#pragma unroll
+    for (int kt = 0; kt < 2; ++kt)
+        o = mfma(ld8(&w.ha[l & 15][kt * 32 + 8 * (l >> 4)]), ld8(&P.w4t[l & 15][kt * 32 + 8 * (l >> 4)]), o);
+    out[0] = o;
+}
+
 __global__ __launch_bounds__(kBlock) void k_mlp_pack(const float* __restrict__ m, Packed* __restrict__ p)
 {
     const int t = blockIdx.x * blockDim.x + threadIdx.x;
@@ -204,22 +262,26 @@ __global__ __launch_bounds__(kBlock) void k_mlp_pack(const float* __restrict__ m
 }
 
 // inference: y[n][2]; hidden (optional) = three [n][64] BF16 activation arrays
-__global__ __launch_bounds__(kBlock) void k_mlp_fwd(const Packed* __restrict__ gp, const float* __restrict__ x,
-                                                    int64_t n, float* __restrict__ y, bf16* __restrict__ hidden)
+__global__ __launch_bounds__(kFwdBlock) void k_mlp_fwd(const Packed* __restrict__ gp, const float* __restrict__ x,
+                                                       int64_t n, float* __restrict__ y, bf16* __restrict__ hidden)
 {
     __shared__ PackedFwd P;
-    __shared__ WaveLds wl[kBlock / 64];
+    __shared__ FwdLds wl[kFwdBlock / 64];
     stage_params(P, gp);
     __syncthreads();
-    WaveLds& w = wl[threadIdx.x >> 6];
+    FwdLds& w = wl[threadIdx.x >> 6];
     const int l = lane();
+    for (int k = l; k < kTile * 32; k += 64) w.x[k >> 5][k & 31] = bf16(0.0f);
     const int64_t tiles = (n + kTile - 1) / kTile;
-    for (int64_t t = int64_t(blockIdx.x) * (kBlock / 64) + (threadIdx.x >> 6); t < tiles;
-         t += int64_t(gridDim.x) * (kBlock / 64)) {
+    const int64_t t0 = int64_t(blockIdx.x) * (kFwdBlock / 64) + (threadIdx.x >> 6);
+    const int64_t stride = int64_t(gridDim.x) * (kFwdBlock / 64);
+    XFetch xf = fetch_x(x, t0 * kTile, n);
+    for (int64_t t = t0; t < tiles; t += stride) {
         const int64_t s0 = t * kTile;
+        const XFetch cur = xf;
+        xf = fetch_x(x, (t + stride) * kTile, n);   // the next tile's inputs, in flight meanwhile
         f32x4 o[1];
-        forward_tile(P, w, x, s0, n, n, hidden ? hidden : nullptr, hidden ? hidden + n * kH : nullptr,
-                     hidden ? hidden + 2 * n * kH : nullptr, o);
+        forward_tile_inf(P, w, cur, s0, n, hidden, o);
         if ((l & 15) < kOut)
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
@@ -528,7 +590,7 @@ pc_status pc_mlp_forward(const void* packed, const float* x, int64_t n, float* y
     }
     if (n == 0) return PC_OK;
     const int64_t tiles = (n + kTile - 1) / kTile;
-    hipLaunchKernelGGL(k_mlp_fwd, dim3(grid_for((tiles + 3) / 4)), dim3(kBlock), 0,
+    hipLaunchKernelGGL(k_mlp_fwd, dim3(grid_for((tiles + 7) / 8)), dim3(kFwdBlock), 0,
                        static_cast<hipStream_t>(stream), static_cast<const Packed*>(packed), x, n, y,
                        reinterpret_cast<bf16*>(hidden));
     return hipGetLastError() == hipSuccess ? PC_OK : PC_ERR_HIP;
