@@ -375,7 +375,7 @@ def main() -> int:
     if not args.no_fluid:
         out["fluid"] = measure_fluid(args, elapsed * 1e3 / args.steps, float(cfg["dt"]))
     if not args.no_cpu:
-        steps = args.cpu_steps or max(5, int(4.0e8 / (ne_avg + ni_avg / S)))
+        steps = args.cpu_steps or max(5, int(6.0e8 / (ne_avg + ni_avg / S)))
         print(f"[bench] cpu baseline: oracle, {steps} steps", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(cfg, steps)
     if args.copy_mib > 0:
