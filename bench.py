@@ -300,7 +300,7 @@ def main() -> int:
     ap.add_argument("--no-batch", action="store_true", help="skip the batched argon scan")
     ap.add_argument("--no-tune", action="store_true", help="batched scan without the autotuner")
     ap.add_argument("--batch-columns", type=int, default=64)
-    ap.add_argument("--batch-steps", type=int, default=200)
+    ap.add_argument("--batch-steps", type=int, default=320)
     ap.add_argument("--batch-warmup", type=int, default=40)
     ap.add_argument("--no-fluid", action="store_true", help="skip the batched fluid columns")
     ap.add_argument("--fluid-columns", type=int, default=256)

@@ -1063,7 +1063,8 @@ pc_status enqueue_batch_step(pc_batch* b, bool time_it, int64_t slot)
     if (ion) b->ri_cur = 1 - b->ri_cur;
     b->step += 1;
     if (b->K > 0 && b->step % b->K == 0) {
-        for (int s = 0; s < 2; ++s) {
+        const bool ions = b->step % (int64_t(b->K) * kIonSortEvery) == 0;
+        for (int s = 0; s < (ions ? 2 : 1); ++s) {
             HIPCHK(pclaunch::batch_sort(b->dcols, n, b->fp32, s, b->ditems[s], b->n_items[s], b->cur[s], b->st));
             b->cur[s] = 1 - b->cur[s];
         }
@@ -1075,7 +1076,7 @@ int64_t batch_period(const pc_batch* b)
 {
     auto lcm = [](int64_t a, int64_t c) { return a / gcd64(a, c) * c; };
     int64_t p = lcm(2, 2 * int64_t(b->S));
-    if (b->K > 0) p = lcm(p, 2 * int64_t(b->K));
+    if (b->K > 0) p = lcm(p, 2 * kIonSortEvery * int64_t(b->K));
     return p;
 }
 

@@ -95,9 +95,9 @@ def test_batch_columns_equal_single_columns(torch_cuda, precision):
 def test_full_size_scan_members_equal_single_columns(torch_cuda):
     # the bench's batched workload: the 64-column argon scan (1000-8000
     # cells, 100-400 per cell, 82M + 82M FP32 particles) with the bench's
-    # tuned setting (4096-particle chunks, sort every 80 steps); after one
-    # graph period (160 steps) the smallest, the largest and the first column
-    # are bitwise the same column stepped alone
+    # tuned setting (4096-particle chunks, sort every 80 steps); after 160
+    # steps the smallest, the largest and the first column are bitwise the
+    # same column stepped alone
     cfgs = W.argon_scan(64)
     b = _batch(cfgs)
     b.set_tuning(4096, 80)
