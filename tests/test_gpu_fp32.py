@@ -89,6 +89,12 @@ def _step_parity(cfg, steps):
     return flips
 
 
+def test_fp32_step_parity_column_20cm_full_size(torch_cuda):
+    # the bench's FP32 leg: 400k + 400k particles in the bench's launch grid,
+    # steps 0-2 (an ion step first) from the shared state, every particle
+    _step_parity(W.with_(W.column_20cm(), precision="fp32"), steps=3)
+
+
 def test_fp32_step_parity_bounded(torch_cuda):
     _step_parity(W.with_(W.small_bounded(), precision="fp32"), steps=40)
 
