@@ -278,6 +278,24 @@ def test_step_parity_hot_cathode_and_circuit(torch_cuda):
     assert abs(seen[-1][1] - cfg["V"]) > 0.01             # the resistor moved the anode potential
 
 
+def test_step_parity_full_size_pair_sink_and_hot_cathode(torch_cuda):
+    # the bench's pair-sink leg (the 20 cm column with the paper's pair
+    # removal, 400k + 400k) and its section V leg (the 15 cm bounded column
+    # with emission and the series resistor, 150k + 150k): three shared-state
+    # steps each after 38 steps alone, every particle compared
+    cfg = W.with_(W.column_20cm(), wall_mode="pair")
+    _run_shared_state(torch_cuda, cfg, steps=3, setup=lambda col: col.step(38), min_events={1: 1000})
+    hc = W.hot_cathode_15cm()
+
+    def check(col, orc, k):
+        g = col.counts()
+        o = orc.circuit()
+        assert abs(g["circuit"][0] - o["V_anode"]) <= 1e-12 * abs(hc["V"]), k
+        assert g["circuit"][1] == o["vsum_ion"] and g["circuit"][2] == o["emit_carry"], k
+
+    _run_shared_state(torch_cuda, hc, steps=3, setup=lambda col: col.step(38), check=check, min_events={1: 100})
+
+
 @pytest.mark.parametrize("bc", ["bounded", "periodic"])
 def test_empty_column_steps(torch_cuda, bc):
     # no particles at all: every kernel sees empty chunks; the field is the
