@@ -99,6 +99,38 @@ def test_fluid_steps_against_oracle(torch_cuda, n_cells, steps, tol):
         assert np.abs(E[0] - d["E"]).max() <= 1e-4 * np.abs(d["E"]).max()
 
 
+def test_fluid_full_size_against_oracle(torch_cuda):
+    # the bench's fluid workload: 256 columns x 4096 cells (20 cm, pressures
+    # 0.5-2 Torr, 5 % density modulations), table closure, one launch per
+    # kernel for all columns; after 4 steps columns 0, 127 and 255 against
+    # the oracle
+    table = W.fluid_table_smooth()
+    ncol, ncell, dt, L, steps = 256, 4096, 2.0e-9, 0.20, 4
+    rng = np.random.default_rng(5)
+    spec = []
+    for c in range(ncol):
+        p = float(np.exp(rng.uniform(np.log(0.5), np.log(2.0))))
+        spec.append(dict(L=L, Ngas=3.22e22 * p, E0=300.0 * p * float(rng.uniform(0.9, 1.3)), nu_w=2.0e4 / p,
+                         muiN=4.0e21))
+    x = (np.arange(ncell) + 0.5) / ncell
+    n0 = np.array([1e15 * (1.0 + 0.05 * np.cos(2 * np.pi * (2 + c % 5) * x)) for c in range(ncol)])
+    w0 = 1.5 * n0 * 3.0
+    n0 = n0.astype(np.float32).astype(np.float64)
+    w0 = w0.astype(np.float32).astype(np.float64)
+    from paper_2202_03215_amd.fluid import FluidBatch
+    fb = FluidBatch(spec, ncell, dt, table, W.FLUID_T_MIN, W.FLUID_T_STEP)
+    fb.set_state(n0, w0)
+    fb.step(steps)
+    ng, wg = (t.cpu().numpy().astype(np.float64) for t in fb.get_state())
+    for k in (0, 127, 255):
+        c = F.FluidColumn(n_cells=ncell, T_min=W.FLUID_T_MIN, T_step=W.FLUID_T_STEP, table=table, dt=dt,
+                          **spec[k])
+        n, w = F.run(c, n0[k], w0[k], steps)
+        Tg, To = wg[k] / (1.5 * ng[k]), w / (1.5 * n)
+        assert np.abs(ng[k] - n).max() <= 1e-4 * n.mean(), (k, np.abs(ng[k] - n).max() / n.mean())
+        assert np.abs(Tg - To).max() <= 1e-4 * To.mean(), (k, np.abs(Tg - To).max() / To.mean())
+
+
 def test_fluid_network_closure_against_oracle(torch_cuda):
     from paper_2202_03215_amd.mlp import ClosureNet
     n_cells = 256
