@@ -61,7 +61,7 @@ def _check_layer(g, o, S):
     return int(d.sum())
 
 
-@pytest.mark.parametrize("n", [1, 17, 1000, 4099])
+@pytest.mark.parametrize("n", [1, 17, 1000, 4099, 1 << 20])   # 1 << 20: the fluid bench's 256 x 4096 faces
 def test_forward_layerwise_parity(torch_cuda, n):
     from paper_2202_03215_amd.mlp import bf16_bits_to_float
     torch = torch_cuda
