@@ -124,9 +124,19 @@ def measure(cfg: dict, args, tag: str) -> dict:
     print(f"[bench] {tag}: {args.steps} steps in {elapsed:.3f} s (graphs), {t3 - t2:.3f} s (eager, "
           f"timed); push kernel avg {avg_s * 1e6:.2f} us over {launches} launches",
           file=sys.stderr, flush=True)
+    # diagnostics on demand (cell moments of both species and the EEPF
+    # histogram): host-timed calls, each with its output clear and copy-out
+    col.moments()
+    torch.cuda.synchronize()
+    t4 = time.perf_counter()
+    for _ in range(20):
+        col.moments()
+    torch.cuda.synchronize()
+    moments_us = (time.perf_counter() - t4) * 1e6 / 20
     del col
     torch.cuda.empty_cache()
     return {"value": value, "elapsed": elapsed, "ne": ne_avg, "ni": ni_avg, "ion_steps": ion_steps,
+            "moments_us_per_call": moments_us,
             "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                          "frac": achieved / HBM_PEAK_GBS, "traffic": None,
                          "kernel": "k_push_e<false, Soa32>" if fp32 else "k_push_e<false, Soa>",
@@ -343,6 +353,8 @@ def main() -> int:
         "roofline": r64["roofline"],
         "electron_steps_per_s": ne_avg * args.steps / elapsed,
         "ion_steps_per_s": ni_avg * r64["ion_steps"] / elapsed,
+        "moments": {"us_per_call": r64["moments_us_per_call"],
+                    "what": "cell moments of both species and the EEPF histogram, on demand, host-timed"},
     }
     if args.workload in PUSH_COUNTERS_KIB:
         f, w = PUSH_COUNTERS_KIB[args.workload]

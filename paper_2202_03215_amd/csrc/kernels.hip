@@ -1776,23 +1776,51 @@ __global__ void k_copy_soa(Soa dst, Soa src, int64_t n)
 }
 
 // ----------------------------------------------------------------- moments
+// Adds the lanes' values a[q] into out[(first + q) nc + j]: the lanes whose
+// cell is the first active lane's are summed across the wave and added once
+// (the arrays are sorted by cell, so a wave holds one or two cells), the
+// other active lanes add their own.  Integer sums: the result does not
+// depend on the grouping.
+template <int Q>
+__device__ __forceinline__ void cell_sums(int64_t* out, int nc, int first, bool act, int j, const int64_t a[Q])
+{
+    const uint64_t m = __ballot(act);
+    if (m == 0) return;
+    const int l1 = __ffsll((unsigned long long)m) - 1;
+    const int j1 = __builtin_amdgcn_readlane(j, l1);
+    const bool in1 = act && j == j1;
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+        const uint64_t sum = __ockl_wfred_add_u64(in1 ? uint64_t(a[q]) : 0ull);
+        if (lane_id() == l1) atomicAdd((unsigned long long*)&out[(first + q) * nc + j1], (unsigned long long)sum);
+        if (act && !in1) atomicAdd((unsigned long long*)&out[(first + q) * nc + j], (unsigned long long)a[q]);
+    }
+}
+
 template <class St>
 __global__ __launch_bounds__(256) void k_moments_e(Params P, St sp, int32_t cpg, int64_t* out)
 {
     const int64_t n = P.cnt->n[0];
     const int nc = P.nc;
-    for (int64_t k = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; k < n;
-         k += int64_t(gridDim.x) * blockDim.x) {
-        const int j = cell_at(P, sp, k);
-        double vx, vy, vz;
-        load_v(P, sp, uint32_t(k), kElectron, vx, vy, vz);
-        const double eps = P.c_eps * ((vx * vx + vy * vy) + vz * vz);
-        atomicAdd((unsigned long long*)&out[j], 1ull);
-        atomicAdd((unsigned long long*)&out[nc + j], (unsigned long long)int64_t(eps * 1048576.0));
-        atomicAdd((unsigned long long*)&out[2 * nc + j], (unsigned long long)int64_t(vx * 1024.0));
-        atomicAdd((unsigned long long*)&out[3 * nc + j], (unsigned long long)int64_t(eps * vx * 16.0));
-        const int b = int(eps * 4.0);
-        if (b < 240) atomicAdd((unsigned long long*)&out[7 * nc + (j / cpg) * 240 + b], 1ull);
+    const int64_t stride = int64_t(gridDim.x) * blockDim.x;
+    for (int64_t k0 = int64_t(blockIdx.x) * blockDim.x; k0 < n; k0 += stride) {
+        const int64_t k = k0 + threadIdx.x;
+        const bool act = k < n;
+        int j = 0, b = 240;
+        int64_t a[4] = {0, 0, 0, 0};
+        if (act) {
+            j = cell_at(P, sp, k);
+            double vx, vy, vz;
+            load_v(P, sp, uint32_t(k), kElectron, vx, vy, vz);
+            const double eps = P.c_eps * ((vx * vx + vy * vy) + vz * vz);
+            a[0] = 1;
+            a[1] = int64_t(eps * 1048576.0);
+            a[2] = int64_t(vx * 1024.0);
+            a[3] = int64_t(eps * vx * 16.0);
+            b = int(eps * 4.0);
+        }
+        cell_sums<4>(out, nc, 0, act, j, a);
+        if (act && b < 240) atomicAdd((unsigned long long*)&out[7 * nc + (j / cpg) * 240 + b], 1ull);
     }
 }
 
@@ -1801,13 +1829,20 @@ __global__ __launch_bounds__(256) void k_moments_i(Params P, St sp, int64_t* out
 {
     const int64_t n = P.cnt->n[1];
     const int nc = P.nc;
-    for (int64_t k = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; k < n;
-         k += int64_t(gridDim.x) * blockDim.x) {
-        const int j = cell_at(P, sp, k);
-        double vx, vy, vz;
-        load_v(P, sp, uint32_t(k), kIon, vx, vy, vz);
-        atomicAdd((unsigned long long*)&out[4 * nc + j], 1ull);
-        atomicAdd((unsigned long long*)&out[5 * nc + j], (unsigned long long)int64_t(vx * 1024.0));
+    const int64_t stride = int64_t(gridDim.x) * blockDim.x;
+    for (int64_t k0 = int64_t(blockIdx.x) * blockDim.x; k0 < n; k0 += stride) {
+        const int64_t k = k0 + threadIdx.x;
+        const bool act = k < n;
+        int j = 0;
+        int64_t a[2] = {0, 0};
+        if (act) {
+            j = cell_at(P, sp, k);
+            double vx, vy, vz;
+            load_v(P, sp, uint32_t(k), kIon, vx, vy, vz);
+            a[0] = 1;
+            a[1] = int64_t(vx * 1024.0);
+        }
+        cell_sums<2>(out, nc, 4, act, j, a);
     }
     if (blockIdx.x == 0) {
         for (int j = threadIdx.x; j < nc; j += blockDim.x) {
