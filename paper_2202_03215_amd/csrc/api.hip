@@ -442,11 +442,16 @@ static pc_status column_init(const pc_config* cfg, const Derived& d, char* base,
     P.E = reinterpret_cast<double*>(base + L.E);
     P.sort_cnt = reinterpret_cast<int32_t*>(base + L.sort_cnt);
     P.sort_off = reinterpret_cast<int32_t*>(base + L.sort_off);
-    // about one initial particle per thread of the advance kernels (measured
-    // on a 400k-particle column: 1600-2048 blocks 25.8 us per step, 3125
-    // blocks 27.6, 4096 blocks 29.1)
-    h->grid = cfg->launch_blocks > 0 ? cfg->launch_blocks
-                                     : int(std::min<int64_t>(4096, std::max<int64_t>(1, (d.n0 + 255) / 256)));
+    // about one initial particle per thread of the advance kernels, with 1/32
+    // headroom: a count a little above the initial one still gives every
+    // block at most one 256-particle tile (the partition rounds chunks up to
+    // multiples of 64, so 1563 blocks for 401k electrons make 320-particle
+    // chunks, a second, nearly empty tile per block).  Measured on the 400k
+    // column: 1563 blocks 26.46 us per step, 1600-1700 blocks 26.1, 3125
+    // blocks 27.6, 4096 blocks 29.1.
+    h->grid = cfg->launch_blocks > 0
+                  ? cfg->launch_blocks
+                  : int(std::min<int64_t>(4096, std::max<int64_t>(1, (d.n0 + d.n0 / 32 + 255) / 256)));
     h->cur[0] = h->cur[1] = 0;
     h->re_cur = h->ri_cur = 0;
     h->use_graphs = 1;
