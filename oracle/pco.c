@@ -25,12 +25,20 @@
  *
  * Build: gcc -O2 -ffp-contract=off -fno-fast-math -shared -fPIC (no FMA
  * contraction, so every product and sum is a separately rounded IEEE op).
+ * The same file built with -fopenmp is the all-core timing build: the
+ * particle loops run in parallel, every shared update is an atomic integer
+ * add or bit-or, the ionizations are sorted by parent id before use and the
+ * charge is an integer sum, so it computes bit for bit what the serial build
+ * computes (without -fopenmp the pragmas are ignored).
  */
 #include "pco.h"
 
 #include <math.h>
 #include <stdlib.h>
 #include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 
 /* CODATA 2018 */
 #define QE   1.602176634e-19
@@ -436,10 +444,16 @@ static void field_update(pco_column* c)
 {
     species_t* e = &c->sp[PCO_ELECTRON];
     species_t* i = &c->sp[PCO_ION];
-    memset(c->rho_e, 0, (size_t)c->nn * sizeof(int64_t));
-    memset(c->rho_i, 0, (size_t)c->nn * sizeof(int64_t));
-    for (int64_t k = 0; k < e->n; ++k) deposit_one(c, e->x[k], c->rho_e);
-    for (int64_t k = 0; k < i->n; ++k) deposit_one(c, i->x[k], c->rho_i);
+    int64_t* re = c->rho_e;
+    int64_t* ri = c->rho_i;
+    const int nn = c->nn;
+    memset(re, 0, (size_t)nn * sizeof(int64_t));
+    memset(ri, 0, (size_t)nn * sizeof(int64_t));
+    /* integer sums: any order of the additions gives the same charge */
+    #pragma omp parallel for schedule(static) reduction(+ : re[:nn])
+    for (int64_t k = 0; k < e->n; ++k) deposit_one(c, e->x[k], re);
+    #pragma omp parallel for schedule(static) reduction(+ : ri[:nn])
+    for (int64_t k = 0; k < i->n; ++k) deposit_one(c, i->x[k], ri);
     if (c->cfg.poisson) {
         pco_solve_field(c, c->rho_e, c->rho_i, NULL, c->E);
     } else {
@@ -467,6 +481,7 @@ int pco_init_column(pco_column* c)
         if (grow(p, n0) || grow_events(p, n0)) return -3;
         const double sig = s == PCO_ELECTRON ? c->sig_e0 : c->sig_i0;
         const uint32_t stream = s == PCO_ELECTRON ? ST_E_INIT : ST_I_INIT;
+        #pragma omp parallel for schedule(static)
         for (int64_t k = 0; k < n0; ++k) {
             uint32_t ctr[4] = {(uint32_t)k, 0u, 0u, stream}, w[4];
             pco_philox4x32_10(ctr, key, w);
@@ -492,6 +507,7 @@ int pco_init_column(pco_column* c)
     for (int s = 0; s < 2; ++s) {
         species_t* p = &c->sp[s];
         const double hq = 0.5 * (s == PCO_ELECTRON ? c->qmdt_e : c->qmdt_i);
+        #pragma omp parallel for schedule(static)
         for (int64_t k = 0; k < p->n; ++k) p->vx[k] = p->vx[k] - hq * gather(c, p->x[k]);
     }
     return 0;
@@ -525,12 +541,19 @@ static int boundary(pco_column* c, double* xp, uint8_t* ev)
         /* reinjection at the opposite end with the same velocity (section II) */
         if (x >= c->L) x -= c->L;
         else if (x < 0.0) { x += c->L; if (x >= c->L) x = 0.0; }
-        if (!(x >= 0.0 && x < c->L)) { c->err |= ERR_RANGE; x = 0.0; }
+        if (!(x >= 0.0 && x < c->L)) {
+            #pragma omp atomic
+            c->err |= ERR_RANGE;
+            x = 0.0;
+        }
         *xp = x;
         return 0;
     }
     if (x >= 0.0 && x < c->L) return 0;
-    if (!(x < 0.0 || x >= c->L)) c->err |= ERR_RANGE;   /* NaN */
+    if (!(x < 0.0 || x >= c->L)) {   /* NaN */
+        #pragma omp atomic
+        c->err |= ERR_RANGE;
+    }
     *ev = PCO_EV_ABSORB;
     return 1;
 }
@@ -539,6 +562,8 @@ static int electron_pass(pco_column* c, uint8_t* dead, const uint32_t key[2])
 {
     species_t* p = &c->sp[PCO_ELECTRON];
     const uint32_t step = (uint32_t)c->step;
+    int failed = 0;
+    #pragma omp parallel for schedule(static)
     for (int64_t k = 0; k < p->n; ++k) {
         uint8_t ev = PCO_EV_NONE;
         double x = p->x[k], vx = p->vx[k];
@@ -563,14 +588,20 @@ static int electron_pass(pco_column* c, uint8_t* dead, const uint32_t key[2])
                 double v2 = (vx * vx + vy * vy) + vz * vz;
                 double eps = c->c_eps * v2;
                 double v = sqrt(v2);
-                if (eps > c->cfg.eps_cap) c->err |= PCO_ERR_ECAP;
+                if (eps > c->cfg.eps_cap) {
+                    #pragma omp atomic
+                    c->err |= PCO_ERR_ECAP;
+                }
                 double s_el = sig_el(c, eps);
                 double s_ex = sig_thomson(eps, c->cfg.ex_U, c->sx4);
                 double s_iz = sig_thomson(eps, c->cfg.iz_U, c->si4);
                 double nu1 = s_el * v * c->Ng;
                 double nu2 = nu1 + s_ex * v * c->Ng;
                 double nu3 = nu2 + s_iz * v * c->Ng;
-                if (nu3 > c->nu_max) c->err |= PCO_ERR_NUMAX;
+                if (nu3 > c->nu_max) {
+                    #pragma omp atomic
+                    c->err |= PCO_ERR_NUMAX;
+                }
                 double R = u1 * c->nu_max;
                 kstream_t ks;
                 ks_init(&ks, key, id, step, ST_E_STEP);
@@ -612,9 +643,14 @@ static int electron_pass(pco_column* c, uint8_t* dead, const uint32_t key[2])
                     b.x = x;
                     b.ve[0] = ve * n2[0]; b.ve[1] = ve * n2[1]; b.ve[2] = ve * n2[2];
                     b.vi[0] = c->sig_a * g[0]; b.vi[1] = c->sig_a * g[1]; b.vi[2] = c->sig_a * g[2];
-                    if (push_birth(c, &b)) return -3;
+                    /* list order is immaterial: the step sorts them by parent id */
+                    #pragma omp critical(pco_births)
+                    {
+                        if (push_birth(c, &b)) failed = 1;
+                    }
                     int j; double f;
                     cell_of(c, x, &j, &f);
+                    #pragma omp atomic
                     c->iz[j] += 1;
                 } else {
                     ev = PCO_EV_NULL;
@@ -626,16 +662,21 @@ static int electron_pass(pco_column* c, uint8_t* dead, const uint32_t key[2])
         p->x[k] = x;
         p->vx[k] = vx;
         dead[k] = (uint8_t)lost;
-        if (!lost && c->cfg.circuit_R > 0.0) c->vs_e += (int64_t)(vpush * 1048576.0);
+        if (!lost && c->cfg.circuit_R > 0.0) {
+            const int64_t dv = (int64_t)(vpush * 1048576.0);
+            #pragma omp atomic
+            c->vs_e += dv;
+        }
         p->ev[id] = ev;
     }
-    return 0;
+    return failed ? -3 : 0;
 }
 
 static void ion_pass(pco_column* c, uint8_t* dead, const uint32_t key[2])
 {
     species_t* p = &c->sp[PCO_ION];
     const uint32_t step = (uint32_t)c->step;
+    #pragma omp parallel for schedule(static)
     for (int64_t k = 0; k < p->n; ++k) {
         uint8_t ev = PCO_EV_NONE;
         double x = p->x[k], vx = p->vx[k];
@@ -664,7 +705,10 @@ static void ion_pass(pco_column* c, uint8_t* dead, const uint32_t key[2])
                 double ax = c->sig_a * g[0], ay = c->sig_a * g[1], az = c->sig_a * g[2];
                 double dx = vx - ax, dy = vy - ay, dz = vz - az;
                 double gr = sqrt((dx * dx + dy * dy) + dz * dz);
-                if (gr > c->cfg.g_cap) c->err |= PCO_ERR_GCAP;
+                if (gr > c->cfg.g_cap) {
+                    #pragma omp atomic
+                    c->err |= PCO_ERR_GCAP;
+                }
                 if (u1 * c->cfg.g_cap < gr) {
                     ev = PCO_EV_CX;
                     vx = ax; vy = ay; vz = az;
@@ -678,7 +722,11 @@ static void ion_pass(pco_column* c, uint8_t* dead, const uint32_t key[2])
         p->x[k] = x;
         p->vx[k] = vx;
         dead[k] = (uint8_t)lost;
-        if (!lost && c->cfg.circuit_R > 0.0) c->vs_ia += (int64_t)(vpush * 1048576.0);
+        if (!lost && c->cfg.circuit_R > 0.0) {
+            const int64_t dv = (int64_t)(vpush * 1048576.0);
+            #pragma omp atomic
+            c->vs_ia += dv;
+        }
         p->ev[id] = ev;
     }
 }
@@ -757,8 +805,8 @@ static int one_step(pco_column* c)
         c->T_we = survival(c->births_last, e->n);
         if (ion_step) c->T_wi = survival(c->births_since_ion, i->n);
     }
-    memset(e->ev, 0, (size_t)e->evcap);
-    memset(i->ev, 0, (size_t)i->evcap);
+    if (e->evcap) memset(e->ev, 0, (size_t)e->evcap);
+    if (i->evcap) memset(i->ev, 0, (size_t)i->evcap);
     c->nb = 0;
     int64_t nmax = e->n > i->n ? e->n : i->n;
     uint8_t* dead = (uint8_t*)calloc((size_t)nmax + 1, 1);
@@ -900,6 +948,17 @@ int pco_step(pco_column* c, int64_t n)
 }
 
 /* -------------------------------------------------------------- accessors */
+int pco_threads(int n)
+{
+#ifdef _OPENMP
+    if (n > 0) omp_set_num_threads(n);
+    return omp_get_max_threads();
+#else
+    (void)n;
+    return 1;
+#endif
+}
+
 int32_t pco_n_nodes(const pco_column* c) { return c ? c->nn : -1; }
 int64_t pco_count(const pco_column* c, int s) { return (c && (s == 0 || s == 1)) ? c->sp[s].n : -1; }
 int64_t pco_step_index(const pco_column* c) { return c ? c->step : -1; }
@@ -925,6 +984,7 @@ int pco_get_state(const pco_column* c, int s, double* x, double* vx, double* vy,
 {
     if (!c || (s != 0 && s != 1)) return -1;
     const species_t* p = &c->sp[s];
+    if (p->n == 0) return 0;   /* nothing to copy (an empty species has no arrays) */
     size_t nb = (size_t)p->n * sizeof(double);
     if (x) memcpy(x, p->x, nb);
     if (vx) memcpy(vx, p->vx, nb);
@@ -945,9 +1005,11 @@ int pco_set_state(pco_column* c, int s, int64_t n, const double* x, const double
         if (!(x[k] >= 0.0 && x[k] < c->L)) return -2;
         if ((int64_t)id[k] + 1 > maxid) maxid = (int64_t)id[k] + 1;
     }
-    size_t nb = (size_t)n * sizeof(double);
-    memcpy(p->x, x, nb); memcpy(p->vx, vx, nb); memcpy(p->vy, vy, nb); memcpy(p->vz, vz, nb);
-    memcpy(p->id, id, (size_t)n * sizeof(uint32_t));
+    if (n > 0) {
+        size_t nb = (size_t)n * sizeof(double);
+        memcpy(p->x, x, nb); memcpy(p->vx, vx, nb); memcpy(p->vy, vy, nb); memcpy(p->vz, vz, nb);
+        memcpy(p->id, id, (size_t)n * sizeof(uint32_t));
+    }
     p->n = n;
     if (maxid > c->next_id[s]) c->next_id[s] = maxid;
     if (grow_events(p, c->next_id[s])) return -3;
@@ -1010,7 +1072,7 @@ int pco_get_events(const pco_column* c, int s, uint8_t* ev, int64_t len)
     if (!c || (s != 0 && s != 1) || !ev) return -1;
     int64_t n = c->next_id[s] < len ? c->next_id[s] : len;
     if (n > c->sp[s].evcap) n = c->sp[s].evcap;
-    memcpy(ev, c->sp[s].ev, (size_t)n);
+    if (n > 0) memcpy(ev, c->sp[s].ev, (size_t)n);
     return 0;
 }
 
@@ -1025,6 +1087,9 @@ int pco_moments(pco_column* c, int32_t cpg, int32_t reset_iz, int64_t* out)
     const int ng = (nc + cpg - 1) / cpg;
     memset(out, 0, (size_t)(7 * nc + ng * 240) * sizeof(int64_t));
     const species_t* e = &c->sp[PCO_ELECTRON];
+    const int64_t len = 7 * (int64_t)nc + (int64_t)ng * 240;
+    (void)len;   /* the reduction's extent (OpenMP build) */
+    #pragma omp parallel for schedule(static) reduction(+ : out[:len])
     for (int64_t k = 0; k < e->n; ++k) {
         int j; double f;
         cell_of(c, e->x[k], &j, &f);
@@ -1038,6 +1103,7 @@ int pco_moments(pco_column* c, int32_t cpg, int32_t reset_iz, int64_t* out)
         if (b < 240) out[7 * nc + (j / cpg) * 240 + b] += 1;
     }
     const species_t* i = &c->sp[PCO_ION];
+    #pragma omp parallel for schedule(static) reduction(+ : out[:len])
     for (int64_t k = 0; k < i->n; ++k) {
         int j; double f;
         cell_of(c, i->x[k], &j, &f);

@@ -73,6 +73,8 @@ int64_t pco_count(const pco_column* c, int species);
 int64_t pco_step_index(const pco_column* c);
 int64_t pco_next_id(const pco_column* c, int species);
 uint32_t pco_errors(const pco_column* c);
+/* threads of the OpenMP timing build (n > 0 sets them); 1 in the serial build */
+int pco_threads(int n);
 /* scalar derived constants: 0 dx, 1 nu_max, 2 P_null, 3 weight W, 4 Ng, 5 P_cx */
 double pco_constant(const pco_column* c, int which);
 

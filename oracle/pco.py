@@ -28,13 +28,14 @@ class pco_config(C.Structure):
         [("seed", C.c_uint64)]
 
 
-_lib = None
+_libs = {}
 
 
-def lib():
-    global _lib
-    if _lib is None:
-        path = _build.ensure()
+def lib(omp: bool = False):
+    """The serial oracle library (parity reference), or with omp=True its
+    OpenMP timing build (same results, all host cores)."""
+    if omp not in _libs:
+        path = _build.ensure(omp)
         L = C.CDLL(path)
         P = C.c_void_p
         d = C.POINTER(C.c_double)
@@ -75,8 +76,15 @@ def lib():
         L.pco_set_field.argtypes = [P, d]
         L.pco_get_events.argtypes = [P, C.c_int, u8, C.c_int64]
         L.pco_moments.argtypes = [P, C.c_int32, C.c_int32, i64]
-        _lib = L
-    return _lib
+        L.pco_threads.argtypes = [C.c_int]
+        L.pco_threads.restype = C.c_int
+        _libs[omp] = L
+    return _libs[omp]
+
+
+def threads(n: int = 0) -> int:
+    """Threads of the OpenMP timing build (n > 0 sets them)."""
+    return int(lib(True).pco_threads(int(n)))
 
 
 def _ptr(a: np.ndarray, ct):
@@ -114,21 +122,22 @@ def make_config(cfg: dict) -> pco_config:
 class Oracle:
     """One oracle column on host memory."""
 
-    def __init__(self, cfg: dict, init: bool = True):
+    def __init__(self, cfg: dict, init: bool = True, omp: bool = False):
         self.cfg = dict(cfg)
         self._c = make_config(cfg)
-        self.h = lib().pco_create(C.byref(self._c))
+        self._L = lib(omp)
+        self.h = self._L.pco_create(C.byref(self._c))
         if not self.h:
             raise ValueError("oracle rejected the config")
         self.nc = int(cfg["n_cells"])
-        self.nn = lib().pco_n_nodes(self.h)
+        self.nn = self._L.pco_n_nodes(self.h)
         if init:
-            self._chk(lib().pco_init_column(self.h))
+            self._chk(self._L.pco_init_column(self.h))
 
     def __del__(self):
         h = getattr(self, "h", None)
         if h:
-            lib().pco_destroy(h)
+            self._L.pco_destroy(h)
             self.h = None
 
     @staticmethod
@@ -137,12 +146,12 @@ class Oracle:
             raise RuntimeError(f"oracle call failed with {rc}")
 
     def step(self, n: int = 1):
-        self._chk(lib().pco_step(self.h, int(n)))
+        self._chk(self._L.pco_step(self.h, int(n)))
 
     def deposit(self, x: np.ndarray) -> np.ndarray:
         x = np.ascontiguousarray(x, dtype=np.float64)
         rho = np.zeros(self.nn, dtype=np.int64)
-        self._chk(lib().pco_deposit(self.h, _ptr(x, C.c_double), x.size, _ptr(rho, C.c_int64)))
+        self._chk(self._L.pco_deposit(self.h, _ptr(x, C.c_double), x.size, _ptr(rho, C.c_int64)))
         return rho
 
     def solve_field(self, rho_e: np.ndarray, rho_i: np.ndarray):
@@ -150,33 +159,33 @@ class Oracle:
         ri = np.ascontiguousarray(rho_i, dtype=np.int64)
         phi = np.zeros(self.nn)
         E = np.zeros(self.nn)
-        self._chk(lib().pco_solve_field(self.h, _ptr(re, C.c_int64), _ptr(ri, C.c_int64),
+        self._chk(self._L.pco_solve_field(self.h, _ptr(re, C.c_int64), _ptr(ri, C.c_int64),
                                         _ptr(phi, C.c_double), _ptr(E, C.c_double)))
         return phi, E
 
     def count(self, s: int) -> int:
-        return int(lib().pco_count(self.h, s))
+        return int(self._L.pco_count(self.h, s))
 
     @property
     def step_index(self) -> int:
-        return int(lib().pco_step_index(self.h))
+        return int(self._L.pco_step_index(self.h))
 
     def next_id(self, s: int) -> int:
-        return int(lib().pco_next_id(self.h, s))
+        return int(self._L.pco_next_id(self.h, s))
 
     @property
     def errors(self) -> int:
-        return int(lib().pco_errors(self.h))
+        return int(self._L.pco_errors(self.h))
 
     def constant(self, name: str) -> float:
         idx = {"dx": 0, "nu_max": 1, "P_null": 2, "W": 3, "Ng": 4, "P_cx": 5}[name]
-        return float(lib().pco_constant(self.h, idx))
+        return float(self._L.pco_constant(self.h, idx))
 
     def state(self, s: int):
         n = self.count(s)
         x, vx, vy, vz = (np.zeros(n) for _ in range(4))
         ids = np.zeros(n, dtype=np.uint32)
-        self._chk(lib().pco_get_state(self.h, s, _ptr(x, C.c_double), _ptr(vx, C.c_double),
+        self._chk(self._L.pco_get_state(self.h, s, _ptr(x, C.c_double), _ptr(vx, C.c_double),
                                       _ptr(vy, C.c_double), _ptr(vz, C.c_double),
                                       _ptr(ids, C.c_uint32)))
         return x, vx, vy, vz, ids
@@ -184,60 +193,60 @@ class Oracle:
     def set_state(self, s: int, x, vx, vy, vz, ids):
         arrs = [np.ascontiguousarray(a, dtype=np.float64) for a in (x, vx, vy, vz)]
         ids = np.ascontiguousarray(ids, dtype=np.uint32)
-        self._chk(lib().pco_set_state(self.h, s, ids.size,
+        self._chk(self._L.pco_set_state(self.h, s, ids.size,
                                       *[_ptr(a, C.c_double) for a in arrs],
                                       _ptr(ids, C.c_uint32)))
 
     def set_counters(self, step: int, next_e: int, next_i: int):
-        self._chk(lib().pco_set_counters(self.h, int(step), int(next_e), int(next_i)))
+        self._chk(self._L.pco_set_counters(self.h, int(step), int(next_e), int(next_i)))
 
     def set_balance(self, births_last: int, births_since_ion: int):
-        self._chk(lib().pco_set_balance(self.h, int(births_last), int(births_since_ion)))
+        self._chk(self._L.pco_set_balance(self.h, int(births_last), int(births_since_ion)))
 
     def balance(self):
         out = np.zeros(2, dtype=np.int64)
-        self._chk(lib().pco_get_balance(self.h, _ptr(out, C.c_int64)))
+        self._chk(self._L.pco_get_balance(self.h, _ptr(out, C.c_int64)))
         return int(out[0]), int(out[1])
 
     def set_circuit(self, V_anode: float, vsum_ion: int, emit_carry: float):
-        self._chk(lib().pco_set_circuit(self.h, float(V_anode), int(vsum_ion), float(emit_carry)))
+        self._chk(self._L.pco_set_circuit(self.h, float(V_anode), int(vsum_ion), float(emit_carry)))
 
     def circuit(self) -> dict:
         """Section V state: anode potential, last conduction current density,
         emission carry and the ions' held v_x sum."""
         out = np.zeros(3)
         vs = np.zeros(1, dtype=np.int64)
-        self._chk(lib().pco_get_circuit(self.h, _ptr(out, C.c_double), _ptr(vs, C.c_int64)))
+        self._chk(self._L.pco_get_circuit(self.h, _ptr(out, C.c_double), _ptr(vs, C.c_int64)))
         return dict(V_anode=float(out[0]), J_cond=float(out[1]), emit_carry=float(out[2]), vsum_ion=int(vs[0]))
 
     def victims(self, species: int) -> np.ndarray:
         """Pair sink: ids removed by the last step, in ionization-rank order."""
-        m = int(lib().pco_get_victims(self.h, species, None, 0))
+        m = int(self._L.pco_get_victims(self.h, species, None, 0))
         out = np.zeros(max(m, 1), dtype=np.uint32)
-        lib().pco_get_victims(self.h, species, _ptr(out, C.c_uint32), m)
+        self._L.pco_get_victims(self.h, species, _ptr(out, C.c_uint32), m)
         return out[:m]
 
     def field(self):
         E = np.zeros(self.nn)
         re = np.zeros(self.nn, dtype=np.int64)
         ri = np.zeros(self.nn, dtype=np.int64)
-        self._chk(lib().pco_get_field(self.h, _ptr(E, C.c_double), _ptr(re, C.c_int64),
+        self._chk(self._L.pco_get_field(self.h, _ptr(E, C.c_double), _ptr(re, C.c_int64),
                                       _ptr(ri, C.c_int64)))
         return E, re, ri
 
     def set_field(self, E: np.ndarray):
         E = np.ascontiguousarray(E, dtype=np.float64)
-        self._chk(lib().pco_set_field(self.h, _ptr(E, C.c_double)))
+        self._chk(self._L.pco_set_field(self.h, _ptr(E, C.c_double)))
 
     def events(self, s: int, length: int | None = None) -> np.ndarray:
         n = self.next_id(s) if length is None else length
         ev = np.zeros(n, dtype=np.uint8)
-        self._chk(lib().pco_get_events(self.h, s, _ptr(ev, C.c_uint8), n))
+        self._chk(self._L.pco_get_events(self.h, s, _ptr(ev, C.c_uint8), n))
         return ev
 
     def moments(self, cells_per_group: int = 1, reset_iz: bool = False) -> np.ndarray:
         ng = (self.nc + cells_per_group - 1) // cells_per_group
         out = np.zeros(7 * self.nc + ng * EEPF_BINS, dtype=np.int64)
-        self._chk(lib().pco_moments(self.h, cells_per_group, int(reset_iz),
+        self._chk(self._L.pco_moments(self.h, cells_per_group, int(reset_iz),
                                     _ptr(out, C.c_int64)))
         return out
