@@ -1,28 +1,37 @@
 """Throughput benchmark of the GPU PIC-MCC column step.
 
-python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME] [--no-cpu]
+python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME] [--no-cpu] ...
 
 Prints one JSON line.  A step is one full time step of the column (electron
 advance with collisions and fused deposit, ion advance on subcycle steps,
 compaction, ionization products, field solve, periodic sort).  `value` is
-particle-steps per second: electrons advanced plus ions advanced (ions only
-on their subcycle steps), over exactly K timed steps with the state resident
-in device memory.  `roofline` reports the electron advance kernel (the
-dominant kernel) against the HBM peak, its duration measured with HIP events
-that take the start and end timestamps of each launch on the library's
-stream (hipExtLaunchKernelGGL), in an eager window of the same length right
-after the graph-replayed one.  `cpu_baseline` times the FP64 CPU oracle on
-a bounded sample of the same workload.  Further objects: `fp32` (FP32
-particles), `pair_sink` (the same column with the paper's own loss model: a
-random electron and ion removed per ionization), `section_v` (the bounded
-15 cm column with a hot cathode and a series resistor), `batched` (64-column
-argon scan) and `fluid` (256 x 4096 fluid columns).
+particle-steps per second of the plain FP64 step on the headline workload
+(column_50cm: neon 0.5 Torr, 50 cm, 5000 cells, 5M + 5M particles):
+electrons advanced plus ions advanced (ions only on their subcycle steps),
+over exactly K timed steps with the state resident in device memory, all K
+replayed from HIP graphs captured beforehand.  `roofline` reports the
+electron advance kernel (the dominant kernel) against the HBM peak and the
+stream probe's rate, its duration measured with HIP events that take the
+start and end timestamps of each launch on the library's stream
+(hipExtLaunchKernelGGL), in an eager window of the same length after the
+graph-replayed one; `traffic` is the kernel's hardware-counter HBM traffic
+from the committed counter profile when that profile was taken on the
+current kernel sources, else null.  `cpu_baseline` times the FP64 CPU oracle
+(serial parity build and OpenMP all-core build) on bounded samples.
+Further objects: `fp32` (the same workload with FP32 particles),
+`column_20cm` (the 400k + 400k column, FP64 and FP32), `pair_sink` (20 cm
+column with the paper's own loss model: a random electron and ion removed
+per ionization), `section_v` (the bounded 15 cm column with a hot cathode and
+a series resistor), `batched` (64-column argon scan, FP32) and `fluid`
+(256 x 4096 fluid columns).
 """
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
+import re
 import sys
 import time
 
@@ -32,38 +41,86 @@ sys.path.insert(0, ROOT)
 import workloads as W  # noqa: E402
 
 HBM_PEAK_GBS = 8000.0   # MI355X HBM3E, GB/s
-
-# rocprofv3 FETCH_SIZE / WRITE_SIZE of the FP64 electron push kernel per launch
-# (KiB) and the counter calibration against a 512 MiB device copy (fetch x2.00,
-# write x1.00); profiles/push_counters_column_20cm_50cm.md.  Valid for the
-# kernel they were taken on only.
-PUSH_COUNTERS_KIB = {"column_20cm": (6803.0, 6905.0), "column_50cm": (79323.0, 82399.0)}
-COUNTER_CAL = (2.00, 1.00)
+METRIC = "particle-steps/s at 1 GPU (plain FP64 vs batched FP32) + % HBM peak"
 
 WORKLOADS = {
-    # Ne 1 Torr, periodic 20 cm, 2000 cells, 200 per cell per species (400k + 400k)
-    "column_20cm": lambda: W.column_20cm(),
     # Ne 0.5 Torr, periodic 50 cm, 5000 cells, 1000 per cell per species (5M + 5M)
     "column_50cm": lambda: W.column_50cm(),
+    # Ne 1 Torr, periodic 20 cm, 2000 cells, 200 per cell per species (400k + 400k)
+    "column_20cm": lambda: W.column_20cm(),
     # Ne 1 Torr, bounded 4 cm, 400 cells, 50 per cell per species (20k + 20k)
     "small_bounded": lambda: W.small_bounded(),
 }
 
+# sources of the particle kernels: a counter profile is valid for the build it was taken on
+KERNEL_SOURCES = ("paper_2202_03215_amd/csrc/kernels.hip", "paper_2202_03215_amd/csrc/device.h")
+
+
+def kernel_source_sha16() -> str:
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def counter_traffic(workload: str, precision: str) -> tuple:
+    """HBM bytes per launch of the electron advance kernel from the committed
+    counter profile (profiles/hbm_counters_push_<workload>_<precision>.md):
+    FETCH_SIZE and WRITE_SIZE per dispatch, each scaled by what the same
+    counter reads for the stream-probe copy of known size.  Null when there
+    is no profile or when it was taken on other kernel sources."""
+    path = os.path.join(ROOT, "profiles", f"hbm_counters_push_{workload}_{precision}.md")
+    if not os.path.exists(path):
+        return None, f"no counter profile for {workload} {precision}"
+    m = re.search(r"```json\s*(\{.*?\})\s*```", open(path).read(), re.S)
+    if not m:
+        return None, f"{os.path.relpath(path, ROOT)} holds no counter record"
+    rec = json.loads(m.group(1))
+    if rec.get("source_sha16") != kernel_source_sha16():
+        return None, (f"{os.path.relpath(path, ROOT)} was taken on kernel sources {rec.get('source_sha16')}, "
+                      f"not the current {kernel_source_sha16()}")
+    t = rec["fetch_kib"] * 1024.0 * rec["fetch_factor"] + rec["write_kib"] * 1024.0 * rec["write_factor"]
+    return t, f"{os.path.relpath(path, ROOT)} (kernel sources {rec['source_sha16']})"
+
 
 def electron_bytes_per_step(p_null: float, fp32: bool = False) -> float:
     """Algorithmic HBM bytes per electron per step of the electron advance
-    kernel.  FP64: read x, vx and id (u32), write x, vx; candidates (a
-    fraction p_null) also list their slot (u32) and read vy, vz.  FP32: read
-    cell, offset, vx, id, write cell, offset, vx (4 B each); candidates list
-    their slot and read vy, vz (4 B each)."""
+    kernel.  FP64: read x, vx (8 B each) and id (4 B), write x, vx; a
+    collision candidate (fraction p_null) also reads and writes vy, vz:
+    36 + 32 p_null.  FP32: read cell, offset, vx, id, write cell, offset, vx
+    (4 B each); candidates read and write vy, vz: 28 + 16 p_null."""
     if fp32:
-        return 16 + 12 + p_null * (4 + 8)
-    return 8 + 8 + 4 + 8 + 8 + p_null * (4 + 16)
+        return 28 + 16 * p_null
+    return 36 + 32 * p_null
 
 
-def cpu_baseline(cfg: dict, steps: int) -> dict:
-    from oracle.pco import Oracle
-    o = Oracle(cfg)
+def cpu_model() -> str:
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def host_threads() -> int:
+    """Host cores this process may use: the OpenMP thread setting of the
+    environment if there is one, else the CPUs of its affinity mask."""
+    n = len(os.sched_getaffinity(0))
+    env = os.environ.get("OMP_NUM_THREADS", "")
+    return max(1, min(n, int(env))) if env.isdigit() and int(env) > 0 else n
+
+
+def oracle_rate(cfg: dict, steps: int, threads: int) -> dict:
+    """Particle-steps/s of the FP64 oracle over `steps` steps from the initial
+    load (serial parity build for threads == 1, else the OpenMP build)."""
+    from oracle import pco
+    omp = threads > 1
+    if omp:
+        pco.threads(threads)
+    o = pco.Oracle(cfg, omp=omp)
     n0e, n0i = o.count(0), o.count(1)
     S = int(cfg["ion_subcycle"])
     t0 = time.perf_counter()
@@ -72,14 +129,35 @@ def cpu_baseline(cfg: dict, steps: int) -> dict:
     ne = 0.5 * (n0e + o.count(0)) * steps
     ion_steps = sum(1 for k in range(steps) if k % S == 0)
     ni = 0.5 * (n0i + o.count(1)) * ion_steps
-    return {"value": (ne + ni) / dt, "unit": "particle-steps/s", "cores": 1, "kind": "oracle",
-            "sample": f"{steps} steps from the initial load of the same workload, serial FP64 "
-                      f"oracle ({dt:.1f} s)"}
+    used = pco.threads() if omp else 1
+    del o
+    return {"value": (ne + ni) / dt, "seconds": dt, "steps": steps, "cores": used}
 
 
-def measure(cfg: dict, args, tag: str) -> dict:
-    """Graph-replayed timed window (throughput) then an eager event-timed
-    window of the same length (electron push kernel duration)."""
+def cpu_baseline(cfg: dict, workload: str, steps_serial: int, steps_omp: int) -> dict:
+    threads = host_threads()
+    print(f"[bench] cpu baseline: oracle {workload}, {steps_serial} steps serial, {steps_omp} steps on "
+          f"{threads} threads", file=sys.stderr, flush=True)
+    ser = oracle_rate(cfg, steps_serial, 1)
+    allc = oracle_rate(cfg, steps_omp, threads) if threads > 1 else ser
+    small = W.small_bounded()
+    m1s = oracle_rate(small, 2000, 1)
+    m1a = oracle_rate(small, 2000, threads) if threads > 1 else m1s
+    return {"value": allc["value"], "unit": "particle-steps/s", "cores": allc["cores"], "kind": "oracle",
+            "sample": f"{allc['steps']} steps of {workload} from its initial load, OpenMP build of the FP64 "
+                      f"oracle on {allc['cores']} threads ({allc['seconds']:.1f} s)",
+            "serial": {"value": ser["value"], "cores": 1,
+                       "sample": f"{ser['steps']} steps of {workload}, serial parity build ({ser['seconds']:.1f} s)"},
+            "small_bounded_2000_steps": {"serial": m1s["value"], "all_cores": m1a["value"],
+                                         "cores": m1a["cores"]},
+            "host": {"cpu_model": cpu_model(), "cpus": os.cpu_count(),
+                     "affinity": len(os.sched_getaffinity(0)), "threads_used": allc["cores"]}}
+
+
+def measure(cfg: dict, args, tag: str, workload: str) -> dict:
+    """Graph-replayed timed window (throughput; the graphs are captured
+    before it) then an eager event-timed window of the same length (electron
+    advance kernel duration)."""
     import torch
     from paper_2202_03215_amd.column import Column
 
@@ -89,6 +167,7 @@ def measure(cfg: dict, args, tag: str) -> dict:
     col.step(args.warmup)
     col.sync()
     c0 = col.counts()
+    col.prepare_graphs(args.steps)
     print(f"[bench] {tag}: warmup {args.warmup} done, n = {c0['n']}", file=sys.stderr, flush=True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -118,32 +197,65 @@ def measure(cfg: dict, args, tag: str) -> dict:
     col.sync()
     ne_avg2 = 0.5 * (c1["n"][0] + c2["n"][0])
     fp32 = cfg.get("precision", "fp64") == "fp32"
-    bytes_per_launch = ne_avg2 * electron_bytes_per_step(float(col.sizes.p_null), fp32)
+    p_null = float(col.sizes.p_null)
+    bpe = electron_bytes_per_step(p_null, fp32)
+    bytes_per_launch = ne_avg2 * bpe
     avg_s = ker_ms * 1e-3 / max(launches, 1)
     achieved = bytes_per_launch / avg_s / 1e9
-    print(f"[bench] {tag}: {args.steps} steps in {elapsed:.3f} s (graphs), {t3 - t2:.3f} s (eager, "
+    print(f"[bench] {tag}: {args.steps} steps in {elapsed:.4f} s (graphs), {t3 - t2:.4f} s (eager, "
           f"timed); push kernel avg {avg_s * 1e6:.2f} us over {launches} launches",
           file=sys.stderr, flush=True)
-    # diagnostics on demand (cell moments of both species and the EEPF
-    # histogram): host-timed calls, each with its output clear and copy-out
-    col.moments()
-    torch.cuda.synchronize()
-    t4 = time.perf_counter()
-    for _ in range(20):
+    traffic, tnote = counter_traffic(workload, "fp32" if fp32 else "fp64")
+    moments_us = None
+    if args.moments:
+        # diagnostics on demand (cell moments of both species and the EEPF
+        # histogram): host-timed calls, each with its output clear and copy-out
         col.moments()
-    torch.cuda.synchronize()
-    moments_us = (time.perf_counter() - t4) * 1e6 / 20
+        torch.cuda.synchronize()
+        t4 = time.perf_counter()
+        for _ in range(20):
+            col.moments()
+        torch.cuda.synchronize()
+        moments_us = (time.perf_counter() - t4) * 1e6 / 20
     del col
     torch.cuda.empty_cache()
     return {"value": value, "elapsed": elapsed, "ne": ne_avg, "ni": ni_avg, "ion_steps": ion_steps,
             "moments_us_per_call": moments_us,
             "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                         "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                         "frac": achieved / HBM_PEAK_GBS, "traffic": traffic, "traffic_source": tnote,
                          "kernel": "k_push_e<false, Soa32>" if fp32 else "k_push_e<false, Soa>",
                          "avg_us": avg_s * 1e6, "launches": launches,
+                         "bytes_per_electron": bpe, "p_null": p_null,
                          "bytes_per_launch": bytes_per_launch,
                          "window": "eager timed window of the same length after the graph window",
                          "ms_per_step_eager": (t3 - t2) * 1e3 / args.steps}}
+
+
+def stream_probe(mib: int = 2048, reps: int = 10) -> dict:
+    """Achievable copy rate of the particle kernels' access form: the
+    library's stream-probe kernel (one 8-byte element per lane) copying
+    `mib` MiB, timed with events over `reps` launches."""
+    import torch
+    from paper_2202_03215_amd.column import stream_probe as probe
+    n = mib * (1 << 20) // 8
+    src = torch.ones(n, dtype=torch.float64, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(2):
+        probe(src, dst)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        probe(src, dst)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1)
+    ok = bool(torch.equal(src, dst))
+    del src, dst
+    torch.cuda.empty_cache()
+    gbs = 2.0 * n * 8 * reps / (ms * 1e-3) / 1e9
+    print(f"[bench] stream probe: {gbs:.0f} GB/s ({mib} MiB copy)", file=sys.stderr, flush=True)
+    return {"GB_s": gbs, "bytes_per_launch": 2.0 * n * 8, "launches": reps, "copy_ok": ok,
+            "kernel": "k_stream_copy (one 8-byte element per lane, 4096 blocks)"}
 
 
 def measure_sequential(cfgs: list, steps: int = 160, warmup: int = 160) -> dict:
@@ -160,6 +272,7 @@ def measure_sequential(cfgs: list, steps: int = 160, warmup: int = 160) -> dict:
         col.step(warmup)
         col.sync()
         n0 = col.counts()
+        col.prepare_graphs(steps)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         col.step(steps)
@@ -224,7 +337,8 @@ def measure_batch(cfgs: list, args) -> dict:
     ne2, _ = totals()
     from paper_2202_03215_amd import native as N
     p_null = [float(N.query_sizes(c).p_null) for c in cfgs]
-    bytes_per_launch = 0.5 * (ne1 + ne2) * electron_bytes_per_step(max(p_null), True)
+    bpe = electron_bytes_per_step(max(p_null), True)
+    bytes_per_launch = 0.5 * (ne1 + ne2) * bpe
     avg_s = ker_ms * 1e-3 / max(launches, 1)
     achieved = bytes_per_launch / avg_s / 1e9
     print(f"[bench] batch: {args.batch_steps} steps in {elapsed:.3f} s (graphs), {t3 - t2:.3f} s "
@@ -237,7 +351,7 @@ def measure_batch(cfgs: list, args) -> dict:
             "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                          "frac": achieved / HBM_PEAK_GBS, "traffic": None,
                          "kernel": "k_batch_push_e<Soa32>", "avg_us": avg_s * 1e6, "launches": launches,
-                         "bytes_per_launch": bytes_per_launch,
+                         "bytes_per_electron": bpe, "bytes_per_launch": bytes_per_launch,
                          "window": "eager timed window of the same length after the graph window"}}
 
 
@@ -300,10 +414,12 @@ def main() -> int:
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=2000)
     ap.add_argument("--warmup", type=int, default=200)
-    ap.add_argument("--workload", default="column_20cm", choices=sorted(WORKLOADS))
+    ap.add_argument("--workload", default="column_50cm", choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
-    ap.add_argument("--cpu-steps", type=int, default=0, help="oracle sample length (0 = auto)")
+    ap.add_argument("--cpu-steps", type=int, default=0,
+                    help="oracle steps of the headline workload (0 = 40 serial, 100 all-core)")
     ap.add_argument("--no-fp32", action="store_true", help="skip the FP32 variant")
+    ap.add_argument("--no-20cm", action="store_true", help="skip the 20 cm column legs")
     ap.add_argument("--no-pair", action="store_true", help="skip the pair-sink variant")
     ap.add_argument("--no-section-v", action="store_true",
                     help="skip the bounded hot-cathode column with the external circuit")
@@ -316,8 +432,10 @@ def main() -> int:
     ap.add_argument("--fluid-columns", type=int, default=256)
     ap.add_argument("--fluid-steps", type=int, default=200)
     ap.add_argument("--fluid-warmup", type=int, default=20)
-    ap.add_argument("--copy-mib", type=int, default=0,
-                    help="also run a plain device copy of this many MiB (counter calibration)")
+    ap.add_argument("--no-probe", action="store_true", help="skip the stream probe")
+    ap.add_argument("--probe-mib", type=int, default=2048)
+    ap.add_argument("--no-moments", dest="moments", action="store_false",
+                    help="skip the on-demand moments timing")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "the engine runs a column on exactly one GPU (no sharding or "
@@ -325,16 +443,11 @@ def main() -> int:
         return 2
 
     cfg = WORKLOADS[args.workload]()
-    r64 = measure(cfg, args, "fp64")
-    r32 = measure(W.with_(cfg, precision="fp32"), args, "fp32") if not args.no_fp32 else None
-    # the paper's own sink (a random electron and ion removed per ionization)
-    pair_ok = not args.no_pair and cfg["bc"] == "periodic"
-    rpair = measure(W.with_(cfg, wall_mode="pair"), args, "pair") if pair_ok else None
+    r64 = measure(cfg, args, "fp64", args.workload)
     value, elapsed, ne_avg, ni_avg = r64["value"], r64["elapsed"], r64["ne"], r64["ni"]
     S = int(cfg["ion_subcycle"])
-
     out = {
-        "metric": "particle-steps/s at 1 GPU (plain FP64) + % HBM peak",
+        "metric": METRIC,
         "value": value,
         "unit": "particle-steps/s",
         "n_gpus": 1,
@@ -346,31 +459,50 @@ def main() -> int:
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": args.workload, "gas": cfg["gas"], "bc": cfg["bc"],
-                   "n_cells": cfg["n_cells"], "particles_per_cell": cfg["ppc"],
+        "config": {"workload": args.workload, "gas": cfg["gas"], "bc": cfg["bc"], "p_torr": cfg["p_torr"],
+                   "L_m": cfg["L"], "n_cells": cfg["n_cells"], "particles_per_cell": cfg["ppc"],
                    "electrons": int(ne_avg), "ions": int(ni_avg), "dt": cfg["dt"],
-                   "ion_subcycle": S, "sort_interval": cfg["sort_interval"]},
+                   "ion_subcycle": S, "sort_interval": cfg["sort_interval"], "precision": "fp64",
+                   "graph_replayed": True},
         "roofline": r64["roofline"],
         "electron_steps_per_s": ne_avg * args.steps / elapsed,
         "ion_steps_per_s": ni_avg * r64["ion_steps"] / elapsed,
-        "moments": {"us_per_call": r64["moments_us_per_call"],
-                    "what": "cell moments of both species and the EEPF histogram, on demand, host-timed"},
     }
-    if args.workload in PUSH_COUNTERS_KIB:
-        f, w = PUSH_COUNTERS_KIB[args.workload]
-        out["roofline"]["traffic"] = (f * COUNTER_CAL[0] + w * COUNTER_CAL[1]) * 1024.0
-        out["roofline"]["traffic_unit"] = "bytes per launch (calibrated FETCH_SIZE + WRITE_SIZE)"
-    if r32 is not None:
+    if r64["moments_us_per_call"] is not None:
+        out["moments"] = {"us_per_call": r64["moments_us_per_call"],
+                          "what": "cell moments of both species and the EEPF histogram, on demand, host-timed"}
+    if not args.no_probe:
+        probe = stream_probe(args.probe_mib)
+        out["stream_probe"] = probe
+        out["roofline"]["peak_measured_copy"] = probe["GB_s"]
+        out["roofline"]["frac_of_measured_copy"] = out["roofline"]["achieved"] / probe["GB_s"]
+    if not args.no_fp32:
+        r32 = measure(W.with_(cfg, precision="fp32"), args, "fp32", args.workload)
         out["fp32"] = {"value": r32["value"], "ms_per_step": r32["elapsed"] * 1e3 / args.steps,
                        "dtype": "f32 particles, f64 field", "roofline": r32["roofline"],
                        "speedup_vs_fp64": r32["value"] / value}
-    if rpair is not None:
-        out["pair_sink"] = {"value": rpair["value"], "ms_per_step": rpair["elapsed"] * 1e3 / args.steps,
-                            "dtype": "f64", "wall_mode": "pair", "roofline": rpair["roofline"],
-                            "relative_to_fixed_sink": rpair["value"] / value}
+    if not args.no_20cm and args.workload != "column_20cm":
+        c20 = W.column_20cm()
+        a = measure(c20, args, "20cm fp64", "column_20cm")
+        leg = {"workload": "column_20cm", "value": a["value"], "ms_per_step": a["elapsed"] * 1e3 / args.steps,
+               "dtype": "f64", "electrons": int(a["ne"]), "ions": int(a["ni"]), "roofline": a["roofline"]}
+        if not args.no_fp32:
+            b = measure(W.with_(c20, precision="fp32"), args, "20cm fp32", "column_20cm")
+            leg["fp32"] = {"value": b["value"], "ms_per_step": b["elapsed"] * 1e3 / args.steps,
+                           "roofline": b["roofline"], "speedup_vs_fp64": b["value"] / a["value"]}
+        out["column_20cm"] = leg
+    if not args.no_pair:
+        # the paper's own sink (a random electron and ion removed per ionization)
+        c20 = W.column_20cm()
+        base = out.get("column_20cm", {}).get("value") if args.workload != "column_20cm" else value
+        rp = measure(W.with_(c20, wall_mode="pair"), args, "pair", "column_20cm")
+        out["pair_sink"] = {"workload": "column_20cm", "value": rp["value"],
+                            "ms_per_step": rp["elapsed"] * 1e3 / args.steps, "dtype": "f64", "wall_mode": "pair",
+                            "roofline": rp["roofline"],
+                            "relative_to_fixed_sink": rp["value"] / base if base else None}
     if not args.no_section_v:
         hc = W.hot_cathode_15cm()
-        rv = measure(hc, args, "section_v")
+        rv = measure(hc, args, "section_v", "hot_cathode_15cm")
         out["section_v"] = {"workload": "hot_cathode_15cm", "value": rv["value"],
                             "ms_per_step": rv["elapsed"] * 1e3 / args.steps, "dtype": "f64",
                             "electrons": int(rv["ne"]), "ions": int(rv["ni"]), "roofline": rv["roofline"]}
@@ -385,22 +517,13 @@ def main() -> int:
                           "sequential_fp64_columns": rs,
                           "speedup_vs_sequential_fp64_columns": rb["value"] / rs["value"]}
     if not args.no_fluid:
-        out["fluid"] = measure_fluid(args, elapsed * 1e3 / args.steps, float(cfg["dt"]))
+        ref = out.get("column_20cm")
+        pic_ms = ref["ms_per_step"] if ref else elapsed * 1e3 / args.steps
+        out["fluid"] = measure_fluid(args, pic_ms, float(W.column_20cm()["dt"]))
     if not args.no_cpu:
-        steps = args.cpu_steps or max(5, int(6.0e8 / (ne_avg + ni_avg / S)))
-        print(f"[bench] cpu baseline: oracle, {steps} steps", file=sys.stderr, flush=True)
-        out["cpu_baseline"] = cpu_baseline(cfg, steps)
-    if args.copy_mib > 0:
-        # a plain copy kernel of known size: its FETCH_SIZE / WRITE_SIZE under
-        # rocprofv3 --pmc calibrate the counters against bytes moved
-        import torch
-        n = args.copy_mib * (1 << 20) // 4
-        src = torch.ones(n, dtype=torch.float32, device="cuda")
-        dst = torch.empty_like(src)
-        for _ in range(3):
-            dst.copy_(src)
-        torch.cuda.synchronize()
-        out["copy_calibration_mib"] = args.copy_mib
+        ss = args.cpu_steps or 40
+        sa = args.cpu_steps or 100
+        out["cpu_baseline"] = cpu_baseline(cfg, args.workload, ss, sa)
     print(json.dumps(out), flush=True)
     return 0
 

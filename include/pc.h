@@ -143,11 +143,19 @@ pc_status pc_init_column(const pc_config* cfg, void* workspace, size_t bytes,
  * deposit), ions every ion_subcycle steps with dt_i = ion_subcycle dt,
  * removal of losses, append of ionization products (ids by rank of the
  * parent id), field solve; a per-cell counting sort every sort_interval
- * steps (no effect on results).  On a non-null stream, whole periods of
- * lcm(2, 2 ion_subcycle, 2 sort_interval) steps are captured once into a
- * HIP graph and replayed; event buffers or an enabled kernel timer make the
- * launches eager.  Results are bitwise identical either way. */
+ * steps (no effect on results).  On a non-null stream the steps are replayed
+ * from HIP graphs: whole periods of lcm(2, 2 ion_subcycle, 4 sort_interval)
+ * steps (after which every buffer parity returns) and the remainder of
+ * n_steps each as one graph, captured the first time a (phase, length) is
+ * met and cached (at most 64 graphs per column, least recently used
+ * dropped).  Event buffers or an enabled kernel timer make the launches
+ * eager.  Results are bitwise identical either way. */
 pc_status pc_step(pc_handle h, int64_t n_steps);
+
+/* Capture, without executing anything, the graphs that a following
+ * pc_step(h, n_steps) will replay, so that its launches carry no capture
+ * cost (blocking on the host only; the column's state is unchanged). */
+pc_status pc_prepare_graphs(pc_handle h, int64_t n_steps);
 
 /* Deposit n positions (device FP64, all in [0, L)) with linear weighting
  * into rho (device int64[n_nodes], overwritten).  Async. */
@@ -274,6 +282,14 @@ pc_status pc_batch_sync(pc_batch_handle b);
 
 /* Free the batch and its member handles (the workspace stays with the caller). */
 void pc_batch_destroy(pc_batch_handle b);
+
+/* Stream probe (measurement, not part of the model): dst = src over n FP64
+ * device elements (n <= 2^29, arrays must not overlap), with the access form
+ * of the particle kernels -- each of `blocks` 256-thread workgroups (0 =
+ * 4096) walks a contiguous chunk, one 8-byte element per lane -- so that its
+ * bytes per second are the achievable rate of that form and its hardware
+ * counters calibrate the particle kernels' counters.  Async on hip_stream. */
+pc_status pc_stream_probe(const double* src, double* dst, int64_t n, int32_t blocks, void* hip_stream);
 
 const char* pc_status_string(pc_status s);
 const char* pc_last_error(void);

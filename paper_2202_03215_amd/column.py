@@ -98,6 +98,10 @@ class Column:
         N.check(N.lib().pc_step(self.h, int(n)))
         self._out()
 
+    def prepare_graphs(self, n: int) -> None:
+        """Capture the graphs a following step(n) replays (nothing executes)."""
+        N.check(N.lib().pc_prepare_graphs(self.h, int(n)))
+
     def sync(self) -> None:
         N.check(N.lib().pc_sync(self.h))
 
@@ -275,3 +279,13 @@ class Batch:
         n = C.c_int64()
         N.check(N.lib().pc_batch_timer_read(self.h, C.byref(ms), C.byref(n)))
         return float(ms.value), int(n.value)
+
+
+def stream_probe(src: torch.Tensor, dst: torch.Tensor, blocks: int = 0) -> None:
+    """dst = src (FP64 device tensors) by the library's stream-probe kernel
+    on torch's current stream (pc_stream_probe)."""
+    if src.dtype != torch.float64 or dst.dtype != torch.float64 or src.numel() != dst.numel():
+        raise ValueError("stream probe: two FP64 tensors of one size")
+    st = torch.cuda.current_stream(src.device)
+    N.check(N.lib().pc_stream_probe(_ptr(src), _ptr(dst), int(src.numel()), int(blocks),
+                                    C.c_void_p(st.cuda_stream)))

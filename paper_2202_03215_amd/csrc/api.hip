@@ -252,9 +252,14 @@ struct pc_column {
     Counters host_cnt;
     std::vector<hipEvent_t> tev;   // timer pool: 2 events per launch
     int64_t tcount;
-    int use_graphs;                // replay whole buffer periods as a HIP graph
-    hipGraphExec_t gexec;
-    int64_t gkey[6];               // bookkeeping state the graph was captured from
+    int use_graphs;                // replay captured HIP graphs of whole steps
+    struct Graph {
+        int64_t key[6];            // step % period, charge and particle buffer parities, length
+        hipGraphExec_t exec;
+        int64_t used;              // last use (eviction order)
+    };
+    std::vector<Graph> graphs;     // whole periods and shorter remainders, at most kMaxGraphs
+    int64_t graph_clock;
     int batch_member;              // owned and stepped by a batch
     int slots_dirty;               // pair sink: the id -> slot map is rebuilt before the next step
 };
@@ -297,13 +302,15 @@ Soa soa_of(const pc_column* h, int s) { return h->buf[s][h->cur[s]]; }
 // of the arrays changes no result.
 constexpr int kIonSortEvery = 2;
 
-pc_status run_sort(pc_column* h, bool ions)
+pc_status run_sort(pc_column* h, bool ions, bool launch = true)
 {
     for (int s = 0; s < (ions ? 2 : 1); ++s) {
-        if (h->fp32)
-            HIPCHK(pclaunch::sort(h->P, s, h->buf32[s][h->cur[s]], h->buf32[s][1 - h->cur[s]], h->grid, h->st));
-        else
-            HIPCHK(pclaunch::sort(h->P, s, h->buf[s][h->cur[s]], h->buf[s][1 - h->cur[s]], h->grid, h->st));
+        if (launch) {
+            if (h->fp32)
+                HIPCHK(pclaunch::sort(h->P, s, h->buf32[s][h->cur[s]], h->buf32[s][1 - h->cur[s]], h->grid, h->st));
+            else
+                HIPCHK(pclaunch::sort(h->P, s, h->buf[s][h->cur[s]], h->buf[s][1 - h->cur[s]], h->grid, h->st));
+        }
         h->cur[s] = 1 - h->cur[s];
     }
     return PC_OK;
@@ -455,7 +462,7 @@ static pc_status column_init(const pc_config* cfg, const Derived& d, char* base,
     h->cur[0] = h->cur[1] = 0;
     h->re_cur = h->ri_cur = 0;
     h->use_graphs = 1;
-    h->gexec = nullptr;
+    h->graph_clock = 0;
     h->step = 0;
 
     auto cleanup = [&](pc_status st) {
@@ -524,12 +531,21 @@ extern "C" {
 
 // Enqueue one full time step on the column's stream and advance the host-side
 // bookkeeping (step index, charge and sort buffer parities).  With time_it,
-// the electron advance launch is bracketed by timer pair `slot`.
-static pc_status enqueue_step(pc_column* h, bool time_it, int64_t slot)
+// the electron advance launch is bracketed by timer pair `slot`.  With
+// launch false only the bookkeeping advances (the step is replayed from a
+// graph).
+static pc_status enqueue_step(pc_column* h, bool time_it, int64_t slot, bool launch = true)
 {
     const int S = h->cfg.ion_subcycle;
     const int K = h->cfg.sort_interval;
     const bool ion = h->step % S == 0;
+    if (!launch) {
+        h->re_cur = 1 - h->re_cur;
+        if (ion) h->ri_cur = 1 - h->ri_cur;
+        h->step += 1;
+        if (K > 0 && h->step % K == 0) return run_sort(h, h->step % (int64_t(K) * kIonSortEvery) == 0, false);
+        return PC_OK;
+    }
     int64_t* re_new = h->rho[0][1 - h->re_cur];
     int64_t* re_old = h->rho[0][h->re_cur];
     int64_t* ri_use = ion ? h->rho[1][1 - h->ri_cur] : h->rho[1][h->ri_cur];
@@ -576,17 +592,22 @@ static int64_t graph_period(const pc_column* h)
 
 static void drop_graph(pc_column* h)
 {
-    if (h->gexec) (void)hipGraphExecDestroy(h->gexec);
-    h->gexec = nullptr;
+    for (pc_column::Graph& g : h->graphs) (void)hipGraphExecDestroy(g.exec);
+    h->graphs.clear();
 }
 
-// Capture `period` steps from the current bookkeeping state into a graph
-// (host bookkeeping is restored: nothing executes during capture).
-static pc_status capture_period(pc_column* h, int64_t period)
+// cached graphs per column: whole periods for every phase a run starts at
+// plus the shorter remainders of step counts that are not whole periods
+constexpr size_t kMaxGraphs = 64;
+
+// Capture `len` steps from the current bookkeeping state into a graph (host
+// bookkeeping is restored: nothing executes during capture).  On a stream
+// that cannot be captured the column stays eager (use_graphs = 0).
+static pc_status capture_steps(pc_column* h, int64_t len, const int64_t key[6], hipGraphExec_t* out)
 {
+    *out = nullptr;
     const int64_t step = h->step;
     const int re = h->re_cur, ri = h->ri_cur, c0 = h->cur[0], c1 = h->cur[1];
-    drop_graph(h);
     hipError_t e = hipStreamBeginCapture(h->st, hipStreamCaptureModeThreadLocal);
     if (e != hipSuccess) {
         (void)hipGetLastError();
@@ -594,7 +615,7 @@ static pc_status capture_period(pc_column* h, int64_t period)
         return PC_OK;
     }
     pc_status st = PC_OK;
-    for (int64_t k = 0; k < period && st == PC_OK; ++k) st = enqueue_step(h, false, 0);
+    for (int64_t k = 0; k < len && st == PC_OK; ++k) st = enqueue_step(h, false, 0);
     hipGraph_t g = nullptr;
     e = hipStreamEndCapture(h->st, &g);
     h->step = step;
@@ -607,26 +628,32 @@ static pc_status capture_period(pc_column* h, int64_t period)
         return st;
     }
     if (e != hipSuccess) return hip_fail(e, "hipStreamEndCapture");
-    e = hipGraphInstantiate(&h->gexec, g, nullptr, nullptr, 0);
+    hipGraphExec_t x = nullptr;
+    e = hipGraphInstantiate(&x, g, nullptr, nullptr, 0);
     (void)hipGraphDestroy(g);
-    if (e != hipSuccess) {
-        h->gexec = nullptr;
-        return hip_fail(e, "hipGraphInstantiate");
+    if (e != hipSuccess) return hip_fail(e, "hipGraphInstantiate");
+    if (h->graphs.size() >= kMaxGraphs) {   // evict the least recently used
+        size_t old = 0;
+        for (size_t k = 1; k < h->graphs.size(); ++k)
+            if (h->graphs[k].used < h->graphs[old].used) old = k;
+        (void)hipGraphExecDestroy(h->graphs[old].exec);
+        h->graphs.erase(h->graphs.begin() + old);
     }
-    h->gkey[0] = step % period;
-    h->gkey[1] = re;
-    h->gkey[2] = ri;
-    h->gkey[3] = c0;
-    h->gkey[4] = c1;
-    h->gkey[5] = 0;
+    pc_column::Graph G;
+    std::memcpy(G.key, key, sizeof(G.key));
+    G.exec = x;
+    G.used = ++h->graph_clock;
+    h->graphs.push_back(G);
+    *out = x;
     return PC_OK;
 }
 
-pc_status pc_step(pc_handle h, int64_t n_steps)
+// Walk n_steps from the current bookkeeping state: whole periods and the
+// remainder each as one graph (captured when missing), launched if
+// `execute`, else only captured (the bookkeeping is then restored).  Steps
+// that cannot be replayed run eagerly (execute) or are skipped (prepare).
+static pc_status walk_steps(pc_column* h, int64_t n_steps, bool execute)
 {
-    if (!h || n_steps < 0) return fail(PC_ERR_INVALID_ARG, "bad handle or step count");
-    if (h->batch_member) return fail(PC_ERR_INVALID_ARG, "column belongs to a batch: step the batch");
-    if (h->poisoned) return fail(PC_ERR_POISONED, "an earlier device error is pending");
     const int64_t period = graph_period(h);
     const bool timer_on = !h->tev.empty();
     const int64_t tcap = int64_t(h->tev.size() / 2);
@@ -634,32 +661,72 @@ pc_status pc_step(pc_handle h, int64_t n_steps)
     // kernel timer run eagerly (graph-recorded events have no readable time)
     const bool graphs = h->use_graphs && h->st != nullptr && !h->ev[0] && !h->ev[1] &&
                         period <= 4096 && !timer_on;
+    const int64_t step0 = h->step;
+    const int re0 = h->re_cur, ri0 = h->ri_cur, c00 = h->cur[0], c10 = h->cur[1];
+    pc_status s = PC_OK;
+    int64_t left = n_steps;
+    while (left > 0 && s == PC_OK) {
+        if (graphs && h->use_graphs) {
+            const int64_t len = left >= period ? period : left;
+            const int64_t key[6] = {h->step % period, h->re_cur, h->ri_cur, h->cur[0], h->cur[1], len};
+            hipGraphExec_t x = nullptr;
+            for (pc_column::Graph& g : h->graphs)
+                if (std::memcmp(g.key, key, sizeof(key)) == 0) {
+                    x = g.exec;
+                    g.used = ++h->graph_clock;
+                    break;
+                }
+            if (!x) {
+                s = capture_steps(h, len, key, &x);
+                if (s != PC_OK) break;
+                if (!x) continue;   // capture unavailable: eager from now on
+            }
+            if (execute) {
+                const hipError_t e = hipGraphLaunch(x, h->st);
+                if (e != hipSuccess) {
+                    s = hip_fail(e, "hipGraphLaunch");
+                    break;
+                }
+            }
+            for (int64_t k = 0; k < len && s == PC_OK; ++k) s = enqueue_step(h, false, 0, false);
+            left -= len;
+        } else if (execute) {
+            const bool t = timer_on && h->tcount < tcap;
+            s = enqueue_step(h, t, h->tcount);
+            if (t) h->tcount += 1;
+            left -= 1;
+        } else {
+            break;
+        }
+    }
+    if (!execute) {
+        h->step = step0;
+        h->re_cur = re0;
+        h->ri_cur = ri0;
+        h->cur[0] = c00;
+        h->cur[1] = c10;
+    }
+    return s;
+}
+
+pc_status pc_step(pc_handle h, int64_t n_steps)
+{
+    if (!h || n_steps < 0) return fail(PC_ERR_INVALID_ARG, "bad handle or step count");
+    if (h->batch_member) return fail(PC_ERR_INVALID_ARG, "column belongs to a batch: step the batch");
+    if (h->poisoned) return fail(PC_ERR_POISONED, "an earlier device error is pending");
     if (h->slots_dirty) {   // pair sink: slot of every id of the current stores
         if (h->fp32) HIPCHK(pclaunch::slot_map(h->P, h->buf32[0][h->cur[0]], h->buf32[1][h->cur[1]], h->st));
         else HIPCHK(pclaunch::slot_map(h->P, soa_of(h, 0), soa_of(h, 1), h->st));
         h->slots_dirty = 0;
     }
-    int64_t left = n_steps;
-    while (left > 0) {
-        if (graphs && h->use_graphs && left >= period) {
-            const int64_t key[6] = {h->step % period, h->re_cur, h->ri_cur, h->cur[0], h->cur[1], 0};
-            if (!h->gexec || std::memcmp(key, h->gkey, sizeof(key)) != 0) {
-                const pc_status s = capture_period(h, period);
-                if (s != PC_OK) return s;
-                if (!h->gexec) continue;   // capture unavailable: eager from now on
-            }
-            HIPCHK(hipGraphLaunch(h->gexec, h->st));
-            h->step += period;   // every buffer parity is back where it started
-            left -= period;
-        } else {
-            const bool t = timer_on && h->tcount < tcap;
-            const pc_status s = enqueue_step(h, t, h->tcount);
-            if (s != PC_OK) return s;
-            if (t) h->tcount += 1;
-            left -= 1;
-        }
-    }
-    return PC_OK;
+    return walk_steps(h, n_steps, true);
+}
+
+pc_status pc_prepare_graphs(pc_handle h, int64_t n_steps)
+{
+    if (!h || n_steps < 0) return fail(PC_ERR_INVALID_ARG, "bad handle or step count");
+    if (h->batch_member) return fail(PC_ERR_INVALID_ARG, "column belongs to a batch: step the batch");
+    return walk_steps(h, n_steps, false);
 }
 
 pc_status pc_deposit(pc_handle h, const double* x, int64_t n, int64_t* rho)
@@ -926,6 +993,14 @@ const char* pc_status_string(pc_status s)
 }
 
 const char* pc_last_error(void) { return g_last_error.c_str(); }
+
+pc_status pc_stream_probe(const double* src, double* dst, int64_t n, int32_t blocks, void* hip_stream)
+{
+    if (n < 0 || n > (int64_t(1) << 29) || (n > 0 && (!src || !dst)) || blocks < 0 || blocks > 65536)
+        return fail(PC_ERR_INVALID_ARG, "stream probe: 0 <= n <= 2^29, non-null arrays, blocks <= 65536");
+    HIPCHK(pclaunch::stream_copy(src, dst, n, blocks > 0 ? blocks : 4096, static_cast<hipStream_t>(hip_stream)));
+    return PC_OK;
+}
 
 }  // extern "C"
 

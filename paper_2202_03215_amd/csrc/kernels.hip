@@ -1764,6 +1764,27 @@ __global__ void k_fill_i64(int64_t* p, int64_t n, int64_t v)
     if (k < n) p[k] = v;
 }
 
+// Measurement kernel (stream probe): dst = src over n FP64 elements.  Each
+// block walks a contiguous chunk in 256-element tiles with one 8-byte element
+// per lane, the access form of the particle kernels, four tiles in flight.
+__global__ __launch_bounds__(kAdvBlock) void k_stream_copy(const double* __restrict__ src,
+                                                           double* __restrict__ dst, int64_t n)
+{
+    int64_t beg, end;
+    chunk_range(n, int(blockIdx.x), int(gridDim.x), beg, end);
+    const uint32_t ue = uint32_t(end);
+    uint32_t i = uint32_t(beg) + threadIdx.x;
+    for (; i + 3u * kAdvBlock < ue; i += 4u * kAdvBlock) {
+        const double a = ld32(src, i), b = ld32(src, i + kAdvBlock), c = ld32(src, i + 2u * kAdvBlock),
+                     d = ld32(src, i + 3u * kAdvBlock);
+        st32(dst, i, a);
+        st32(dst, i + kAdvBlock, b);
+        st32(dst, i + 2u * kAdvBlock, c);
+        st32(dst, i + 3u * kAdvBlock, d);
+    }
+    for (; i < ue; i += kAdvBlock) st32(dst, i, ld32(src, i));
+}
+
 __global__ void k_copy_soa(Soa dst, Soa src, int64_t n)
 {
     const int64_t k = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
@@ -2331,6 +2352,13 @@ hipError_t deposit(const Params& P, const Soa32& sp, int64_t n, int64_t* rho, hi
     hipError_t e = fill_i64(rho, P.nn, 0, st);
     if (e != hipSuccess || n == 0) return e;
     hipLaunchKernelGGL(k_deposit32, dim3(grid_for(n, 256, 1 << 30)), dim3(256), 0, st, P, sp, n, rho);
+    return hipGetLastError();
+}
+
+hipError_t stream_copy(const double* src, double* dst, int64_t n, int blocks, hipStream_t st)
+{
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_stream_copy, dim3(blocks), dim3(kAdvBlock), 0, st, src, dst, n);
     return hipGetLastError();
 }
 

@@ -31,6 +31,7 @@ hipError_t fill_i64(int64_t* p, int64_t n, int64_t v, hipStream_t st);
 hipError_t deposit(const Params& P, const double* x, int64_t n, int64_t* rho, hipStream_t st);
 hipError_t deposit(const Params& P, const Soa32& sp, int64_t n, int64_t* rho, hipStream_t st);
 hipError_t copy_soa(const Soa& dst, const Soa& src, int64_t n, hipStream_t st);
+hipError_t stream_copy(const double* src, double* dst, int64_t n, int blocks, hipStream_t st);
 hipError_t moments(const Params& P, const Soa& se, const Soa& si, int32_t cpg, int reset, int64_t* out,
                    int64_t out_len, hipStream_t st);
 hipError_t moments(const Params& P, const Soa32& se, const Soa32& si, int32_t cpg, int reset, int64_t* out,

@@ -21,7 +21,7 @@ STATUS = {
 ELECTRON, ION = 0, 1
 
 # every exported symbol of include/*.h
-EXPORTS = ("pc_query_sizes", "pc_init_column", "pc_step", "pc_deposit", "pc_solve_field",
+EXPORTS = ("pc_query_sizes", "pc_init_column", "pc_step", "pc_prepare_graphs", "pc_deposit", "pc_solve_field",
            "pc_moments", "pc_get_counts", "pc_get_state", "pc_set_state", "pc_set_counters", "pc_set_balance",
            "pc_set_circuit",
            "pc_get_field", "pc_set_field", "pc_set_events", "pc_timer_enable",
@@ -29,7 +29,7 @@ EXPORTS = ("pc_query_sizes", "pc_init_column", "pc_step", "pc_deposit", "pc_solv
            "pc_query_batch_sizes", "pc_init_batch", "pc_batch_step", "pc_batch_column",
            "pc_batch_tune", "pc_batch_get_tuning", "pc_batch_set_tuning",
            "pc_batch_timer_enable", "pc_batch_timer_read", "pc_batch_sync", "pc_batch_destroy",
-           "pc_status_string", "pc_last_error",
+           "pc_stream_probe", "pc_status_string", "pc_last_error",
            "pc_mlp_query", "pc_mlp_pack", "pc_mlp_forward", "pc_mlp_grad", "pc_mlp_adam",
            "pc_mlp_last_error",
            "pc_fluid_query", "pc_fluid_init", "pc_fluid_set_state", "pc_fluid_get_state",
@@ -90,6 +90,7 @@ def lib() -> C.CDLL:
         "pc_query_sizes": [C.POINTER(pc_config), C.POINTER(pc_sizes)],
         "pc_init_column": [C.POINTER(pc_config), P, C.c_size_t, P, C.POINTER(P)],
         "pc_step": [P, I64],
+        "pc_prepare_graphs": [P, I64],
         "pc_deposit": [P, P, I64, P],
         "pc_solve_field": [P, P, P, P, P],
         "pc_moments": [P, I32, I32, P],
@@ -115,6 +116,7 @@ def lib() -> C.CDLL:
         "pc_batch_timer_enable": [P, I64],
         "pc_batch_timer_read": [P, C.POINTER(C.c_double), C.POINTER(I64)],
         "pc_batch_sync": [P],
+        "pc_stream_probe": [P, P, I64, I32, P],
     }
     for name, args in sig.items():
         f = getattr(L, name)

@@ -71,3 +71,20 @@ def test_launch_grid_and_sort_interval_invariance(torch_cuda, variant):
 def test_bounded_column_repeatable(torch_cuda):
     cfg = W.small_bounded()
     _same(_run(cfg, 200), _run(cfg, 200))
+
+
+def test_remainder_graphs_equal_eager_launches(torch_cuda):
+    """Step counts that are not whole graph periods replay a graph per
+    (phase, length), some captured ahead by prepare_graphs: bitwise the same
+    as eager launches."""
+    from paper_2202_03215_amd.column import Column
+    cfg = W.tiny(**BASE, sort_interval=3)           # graph period 120
+    col = Column(cfg)
+    col.prepare_graphs(37)
+    for n in (37, 5, 1, 1, 130, 77, 37):            # 288 steps in pieces
+        col.step(n)
+    c = col.counts()
+    assert c["errors"] == 0
+    E, re, ri = col.get_field()
+    a = (c, [gpu_state(col, s) for s in (ELECTRON, ION)], E.cpu().numpy(), re.cpu().numpy(), ri.cpu().numpy())
+    _same(a, _run(cfg, 288, events=True))
