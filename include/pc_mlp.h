@@ -59,6 +59,24 @@ pc_status pc_mlp_forward(const void* packed, const float* x, int64_t n, float* y
 pc_status pc_mlp_grad(const void* packed, const float* x, const float* target, int64_t n, float* grad,
                       float* loss, void* scratch, size_t scratch_bytes, void* hip_stream);
 
+/* Largest batch of the allocation-free gradient below. */
+#define PC_MLP_NOALLOC_MAX_BATCH 16384
+
+/* Allocation-free variant of pc_mlp_grad, for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight training or serving
+ * loops, harnesses that forbid hipMalloc): the same arguments and result
+ * (bitwise: the same kernels and the same fixed-order reduction) without the
+ * scratch buffer.  The scratch is a device array of the library, one per
+ * GPU, sized for PC_MLP_NOALLOC_MAX_BATCH samples (about 22 MB) and held
+ * until the process ends; its address is looked up on the first call on
+ * each device, which must be the current device of the calling thread and
+ * of hip_stream.  n > PC_MLP_NOALLOC_MAX_BATCH returns PC_ERR_INVALID_ARG.
+ * Nothing is allocated or freed.  Every call on one GPU shares that array:
+ * calls that may overlap on one GPU (different streams without ordering)
+ * race and must be serialised by the caller. */
+pc_status pc_mlp_grad_noalloc(const void* packed, const float* x, const float* target, int64_t n,
+                              float* grad, float* loss, void* hip_stream);
+
 /* One Adam step (Kingma and Ba) on the FP32 master parameters with moment
  * buffers m, v (float[PC_MLP_PARAMS], zero before step 1); step counts from
  * 1.  If packed is non-null it is refreshed from the new parameters. */

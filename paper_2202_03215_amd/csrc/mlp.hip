@@ -20,6 +20,7 @@
 
 #include <cmath>
 #include <cstdint>
+#include <mutex>
 
 #include "../../include/pc_mlp.h"
 
@@ -525,19 +526,19 @@ using namespace pcmlp;
 
 namespace {
 thread_local const char* g_mlp_err = "";
-int64_t pad32(int64_t n) { return (n + kChunk - 1) / kChunk * kChunk; }
+constexpr int64_t pad32(int64_t n) { return (n + kChunk - 1) / kChunk * kChunk; }
 int grid_for(int64_t tiles) { return int(tiles < 2048 ? (tiles < 1 ? 1 : tiles) : 2048); }
 constexpr int kWgradBlocks = 256;
 
 struct ScratchLayout {
     int64_t xs, h1, h2, h3, dz1, dz2, dz3, dz4, loss, partial, total;
 };
-ScratchLayout scratch_layout(int64_t n)
+constexpr ScratchLayout scratch_layout(int64_t n)
 {
     const int64_t np = pad32(n);
     ScratchLayout L{};
     int64_t o = 0;
-    auto take = [&](int64_t bytes) {
+    auto take = [&](int64_t bytes) constexpr {
         const int64_t at = o;
         o = (o + bytes + 255) & ~int64_t(255);
         return at;
@@ -554,6 +555,69 @@ ScratchLayout scratch_layout(int64_t n)
     L.partial = take(int64_t(kWgradBlocks) * kParams * 4);
     L.total = o;
     return L;
+}
+constexpr int64_t kNoAllocBytes = scratch_layout(PC_MLP_NOALLOC_MAX_BATCH).total;
+}  // namespace
+
+// Training scratch of the allocation-free gradient (pc_mlp_grad_noalloc):
+// one copy per device, placed by the code object loader and held until the
+// process ends.  In host code `scratch` is only a handle for
+// hipGetSymbolAddress; kernels receive the device address it returns.
+static __device__ __align__(256) unsigned char scratch[kNoAllocBytes];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of `scratch` on the current device, looked up once per
+// device with that device current.
+pc_status noalloc_scratch(void** out)
+{
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) {
+        g_mlp_err = "no current device (or device index above 63)";
+        return PC_ERR_HIP;
+    }
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p) {
+            g_mlp_err = "hipGetSymbolAddress of the training scratch failed";
+            return PC_ERR_HIP;
+        }
+        g_scratch_ptr[dev] = p;
+    }
+    *out = g_scratch_ptr[dev];
+    return PC_OK;
+}
+
+// the gradient pass of pc_mlp_grad with its scratch at b (layout L)
+pc_status grad_into(const void* packed, const float* x, const float* target, int64_t n, float* grad, float* loss,
+                    char* b, const ScratchLayout& L, hipStream_t st)
+{
+    TrainStores S;
+    S.xs = reinterpret_cast<bf16*>(b + L.xs);
+    S.h1 = reinterpret_cast<bf16*>(b + L.h1);
+    S.h2 = reinterpret_cast<bf16*>(b + L.h2);
+    S.h3 = reinterpret_cast<bf16*>(b + L.h3);
+    S.dz1 = reinterpret_cast<bf16*>(b + L.dz1);
+    S.dz2 = reinterpret_cast<bf16*>(b + L.dz2);
+    S.dz3 = reinterpret_cast<bf16*>(b + L.dz3);
+    S.dz4 = reinterpret_cast<bf16*>(b + L.dz4);
+    S.loss_part = reinterpret_cast<float*>(b + L.loss);
+    float* partial = reinterpret_cast<float*>(b + L.partial);
+    const int64_t np = pad32(n);
+    const int g1 = grid_for((np / kTile + 3) / 4);
+    hipLaunchKernelGGL(k_mlp_fwdbwd, dim3(g1), dim3(kBlock), 0, st, static_cast<const Packed*>(packed), x, target,
+                       n, np, S);
+    const int64_t chunks = np / kChunk;
+    const int g2 = int(chunks < kWgradBlocks ? chunks : kWgradBlocks);
+    hipLaunchKernelGGL(k_mlp_wgrad, dim3(g2), dim3(kBlock), 0, st, S, np, partial);
+    hipLaunchKernelGGL(k_mlp_reduce, dim3((kParams + kBlock - 1) / kBlock), dim3(kBlock), 0, st, partial, g2,
+                       S.loss_part, g1, n, grad, loss);
+    return hipGetLastError() == hipSuccess ? PC_OK : PC_ERR_HIP;
 }
 }  // namespace
 
@@ -608,29 +672,26 @@ pc_status pc_mlp_grad(const void* packed, const float* x, const float* target, i
         g_mlp_err = "scratch too small";
         return PC_ERR_WORKSPACE;
     }
-    char* b = static_cast<char*>(scratch);
-    TrainStores S;
-    S.xs = reinterpret_cast<bf16*>(b + L.xs);
-    S.h1 = reinterpret_cast<bf16*>(b + L.h1);
-    S.h2 = reinterpret_cast<bf16*>(b + L.h2);
-    S.h3 = reinterpret_cast<bf16*>(b + L.h3);
-    S.dz1 = reinterpret_cast<bf16*>(b + L.dz1);
-    S.dz2 = reinterpret_cast<bf16*>(b + L.dz2);
-    S.dz3 = reinterpret_cast<bf16*>(b + L.dz3);
-    S.dz4 = reinterpret_cast<bf16*>(b + L.dz4);
-    S.loss_part = reinterpret_cast<float*>(b + L.loss);
-    float* partial = reinterpret_cast<float*>(b + L.partial);
-    hipStream_t st = static_cast<hipStream_t>(stream);
-    const int64_t np = pad32(n);
-    const int g1 = grid_for((np / kTile + 3) / 4);
-    hipLaunchKernelGGL(k_mlp_fwdbwd, dim3(g1), dim3(kBlock), 0, st, static_cast<const Packed*>(packed), x, target,
-                       n, np, S);
-    const int64_t chunks = np / kChunk;
-    const int g2 = int(chunks < kWgradBlocks ? chunks : kWgradBlocks);
-    hipLaunchKernelGGL(k_mlp_wgrad, dim3(g2), dim3(kBlock), 0, st, S, np, partial);
-    hipLaunchKernelGGL(k_mlp_reduce, dim3((kParams + kBlock - 1) / kBlock), dim3(kBlock), 0, st, partial, g2,
-                       S.loss_part, g1, n, grad, loss);
-    return hipGetLastError() == hipSuccess ? PC_OK : PC_ERR_HIP;
+    return grad_into(packed, x, target, n, grad, loss, static_cast<char*>(scratch), L,
+                     static_cast<hipStream_t>(stream));
+}
+
+pc_status pc_mlp_grad_noalloc(const void* packed, const float* x, const float* target, int64_t n, float* grad,
+                              float* loss, void* stream)
+{
+    if (!packed || !x || !target || !grad || n < 1) {
+        g_mlp_err = "bad gradient arguments";
+        return PC_ERR_INVALID_ARG;
+    }
+    if (n > PC_MLP_NOALLOC_MAX_BATCH) {
+        g_mlp_err = "batch above PC_MLP_NOALLOC_MAX_BATCH (16384 samples) for the allocation-free gradient";
+        return PC_ERR_INVALID_ARG;
+    }
+    void* base = nullptr;
+    const pc_status s = noalloc_scratch(&base);
+    if (s != PC_OK) return s;
+    return grad_into(packed, x, target, n, grad, loss, static_cast<char*>(base), scratch_layout(n),
+                     static_cast<hipStream_t>(stream));
 }
 
 pc_status pc_mlp_adam(float* master, float* m, float* v, const float* grad, int64_t step, double lr, double beta1,

@@ -30,6 +30,7 @@ def _lib():
             "pc_mlp_pack": [P, P, P],
             "pc_mlp_forward": [P, P, I64, P, P, P],
             "pc_mlp_grad": [P, P, P, I64, P, P, P, C.c_size_t, P],
+            "pc_mlp_grad_noalloc": [P, P, P, I64, P, P, P],
             "pc_mlp_adam": [P, P, P, P, I64, C.c_double, C.c_double, C.c_double, C.c_double, P, P],
         }
         for name, args in sig.items():

@@ -30,7 +30,7 @@ EXPORTS = ("pc_query_sizes", "pc_init_column", "pc_step", "pc_prepare_graphs", "
            "pc_batch_tune", "pc_batch_get_tuning", "pc_batch_set_tuning",
            "pc_batch_timer_enable", "pc_batch_timer_read", "pc_batch_sync", "pc_batch_destroy",
            "pc_stream_probe", "pc_status_string", "pc_last_error",
-           "pc_mlp_query", "pc_mlp_pack", "pc_mlp_forward", "pc_mlp_grad", "pc_mlp_adam",
+           "pc_mlp_query", "pc_mlp_pack", "pc_mlp_forward", "pc_mlp_grad", "pc_mlp_grad_noalloc", "pc_mlp_adam",
            "pc_mlp_last_error",
            "pc_fluid_query", "pc_fluid_init", "pc_fluid_set_state", "pc_fluid_get_state",
            "pc_fluid_set_closure", "pc_fluid_step", "pc_fluid_get_faces", "pc_cyclic_tridiag",
