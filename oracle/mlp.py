@@ -88,11 +88,20 @@ def loss(theta, x, t, emulate: bool = False):
     return float(np.mean((y - np.asarray(t, dtype=np.float64)) ** 2))
 
 
-def backward(theta, x, t, emulate: bool = True):
-    """Gradient of the mean squared error with respect to theta (flat), and the loss."""
+def backward(theta, x, t, emulate: bool = True, hidden=None):
+    """Gradient of the mean squared error with respect to theta (flat), and the loss.
+
+    hidden (optional): the three hidden activations [a1, a2, a3] to use in
+    place of the oracle's own forward pass (the layer inputs a parity check
+    shares with the GPU); the output layer and the whole backward pass are
+    then computed here from them."""
     W1, b1, W2, b2, W3, b3, W4, b4 = unpack(theta)
     r = bf16 if emulate else (lambda v: np.asarray(v, dtype=np.float64))
-    y, a = forward(theta, x, emulate)
+    if hidden is None:
+        y, a = forward(theta, x, emulate)
+    else:
+        a = [r(x)] + [np.asarray(h, dtype=np.float64) for h in hidden]
+        y = a[3] @ r(W4) + b4
     t = np.asarray(t, dtype=np.float64)
     n = y.shape[0]
     dz = r(2.0 * (y - t) / (n * N_OUT))          # d loss / d output pre-activation

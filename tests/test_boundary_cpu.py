@@ -50,7 +50,7 @@ def test_sizes_scale_with_capacity(native):
     (dict(p_torr=40.0), "PC_ERR_UNSTABLE_CONFIG"),       # nu_max dt > 0.1
     (dict(el_p=1.0), "PC_ERR_INVALID_ARG"),
     (dict(n_cells=1), "PC_ERR_INVALID_ARG"),
-    (dict(n_cells=20000, L=0.2), "PC_ERR_INVALID_ARG"),  # field solve limited to 16384 nodes
+    (dict(n_cells=20000, L=0.2), "PC_ERR_INVALID_ARG"),  # field solve limited to 8192 nodes
     (dict(ppc=0), "PC_ERR_INVALID_ARG"),
 ])
 def test_bad_configs_rejected(native, bad, status):

@@ -5,8 +5,11 @@ Per step from a shared state the differences come only from FP32 rounding of
 the offset within a cell (ulp 6e-8 cell) and of velocities (relative 6e-8 per
 operation): positions agree to 1e-6 cell, velocities to 1e-6 (|v| + v_th),
 and every event agrees except draws within rounding of a threshold (counted;
-at most 1e-4 of the particles).  Charges agree to a few units of 2^-25 per
-particle; the total charge is exact.  Free runs are compared statistically
+at most 1e-4 of the particles).  On a step with such a flip every particle
+present on both sides before the step whose own event agrees is still
+compared (only the flipped ones and the step's products, whose ids may
+differ, are left out).  Charges agree to a few units of 2^-25 per particle;
+the total charge is exactly 2^25 units per particle.  Free runs are compared statistically
 with the FP64 GPU path.
 """
 import math
@@ -52,40 +55,59 @@ def _step_parity(cfg, steps):
     vth = _vth(cfg)
     flips = 0
     total = 0
+    compared = 0
     for k in range(steps):
         copy_gpu_to_oracle(col, orc)
+        pre_next = col.counts()["next_id"]
         ev_e.zero_()
         ev_i.zero_()
         col.step(1)
         orc.step(1)
         c = col.counts()
         assert c["errors"] == 0 and orc.errors == 0
+        flipped = {}
         for s, ev in ((ELECTRON, ev_e), (ION, ev_i)):
             n = orc.next_id(s)
             ge = ev[:n].cpu().numpy()
             oe = orc.events(s, n)
-            flips += int((ge != oe).sum())
+            flipped[s] = np.where(ge != oe)[0]
+            flips += int(flipped[s].size)
             total += n
-        if c["n"] != (orc.count(0), orc.count(1)):
-            continue       # a threshold flip changed the population this step
         for s in (ELECTRON, ION):
             g = gpu_state(col, s)
             o = by_id(orc.state(s))
-            if not np.array_equal(g[4], o[4]):
-                continue
-            d = np.abs(g[0] - o[0])
+            if np.array_equal(g[4], o[4]) and flipped[ELECTRON].size == 0 and flipped[ION].size == 0:
+                gi = oi = slice(None)
+            else:
+                # a draw decided differently (FP32 energy at a threshold): compare
+                # every particle present on both sides that existed before the step
+                # and whose own event agrees; products of the step may differ in id
+                keep = np.intersect1d(g[4], o[4])
+                keep = keep[keep < pre_next[s]]
+                keep = np.setdiff1d(keep, flipped[s])
+                assert keep.size >= 0.99 * min(g[4].size, o[4].size), (k, s, keep.size)
+                gi = np.searchsorted(g[4], keep)
+                oi = np.searchsorted(o[4], keep)
+            d = np.abs(g[0][gi] - o[0][oi])
             d = np.minimum(d, cfg["L"] - d) if cfg["bc"] == "periodic" else d
-            assert d.max() <= 1e-6 * dx, (k, s, d.max() / dx)
+            assert d.max(initial=0.0) <= 1e-6 * dx, (k, s, d.max() / dx)
             for q in (1, 2, 3):
-                rel = np.abs(g[q] - o[q]) / (np.abs(o[q]) + vth[s])
-                assert rel.max() <= 1e-6, (k, s, q, rel.max())
+                rel = np.abs(g[q][gi] - o[q][oi]) / (np.abs(o[q][oi]) + vth[s])
+                assert rel.max(initial=0.0) <= 1e-6, (k, s, q, rel.max())
+            compared += int(d.size)
         Eg, reg, rig = col.get_field()
         Eo, reo, rio = orc.field()
         reg, rig = reg.cpu().numpy(), rig.cpu().numpy()
-        assert reg.sum() == reo.sum() and rig.sum() == rio.sum()
-        assert np.abs(reg - reo).max() <= 64 * (1 + reo.max() // (1 << 25))
-        assert np.abs(rig - rio).max() <= 64 * (1 + rio.max() // (1 << 25))
+        # total charge: 2^25 units per particle, so the two sides differ only by
+        # the particles a flipped draw added or removed
+        assert reg.sum() - reo.sum() == (c["n"][0] - orc.count(0)) << 25, k
+        assert rig.sum() - rio.sum() == (c["n"][1] - orc.count(1)) << 25, k
+        if c["n"] == (orc.count(0), orc.count(1)) and flipped[ELECTRON].size == 0 and flipped[ION].size == 0:
+            assert reg.sum() == reo.sum() and rig.sum() == rio.sum()
+            assert np.abs(reg - reo).max() <= 64 * (1 + reo.max() // (1 << 25))
+            assert np.abs(rig - rio).max() <= 64 * (1 + rio.max() // (1 << 25))
     assert flips <= max(2, 1e-4 * total), flips
+    assert compared > 0
     return flips
 
 

@@ -202,9 +202,13 @@ def test_step_parity_column_50cm_full_size(torch_cuda):
     _run_shared_state(torch_cuda, cfg, steps=2, setup=lambda col: col.step(19), min_events={1: 1000, 7: 50000})
 
 
-def test_step_parity_small_bounded(torch_cuda):
-    # neon, 4 cm, 400 cells, 50 per cell, grounded cathode / 40 V anode
-    _run_shared_state(torch_cuda, W.small_bounded(), steps=60, min_events={1: 50, 5: 20})
+def test_step_parity_small_bounded_all_2000_steps(torch_cuda):
+    # the small workload's whole run (neon, 4 cm, 400 cells, 50 per cell,
+    # grounded cathode / 40 V anode, 2000 steps): every step from the shared
+    # state, every particle, event, charge and the field
+    tot = _run_shared_state(torch_cuda, W.small_bounded(), steps=2000,
+                            min_events={1: 100000, 2: 50, 3: 5, 4: 10, 5: 2000})
+    print("events over 2000 steps", tot)
 
 
 def test_step_parity_periodic_ionizing(torch_cuda):
