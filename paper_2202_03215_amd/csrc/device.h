@@ -50,7 +50,8 @@ struct Counters {
     // bounded column with an external circuit and cathode emission (section V)
     double V;            // anode potential of the next field solve [V]
     double J;            // conduction current density of the last step [A/m^2]
-    int64_t pad2[2];
+    int64_t field_loaded; // finish: step index + 1 once the field half holds that step's charges
+    int64_t pad2;
     int64_t vsum_i;      // ions' sum of v_x (2^-20 m/s units) of the last ion step (held)
     double carry;        // fractional emitted electrons carried to the next step
     int64_t pad1[2];

@@ -1348,10 +1348,50 @@ __device__ void pair_victims(const Params& P, const St& se, const St& si, int64_
     __syncthreads();
 }
 
+// The finish work of a step falls into two independent halves, run by two
+// workgroups of one launch: the field (Poisson solve, external circuit) and
+// the particles (ionization kinematics, hole filling, products, emission,
+// counters).  Products add an electron and an ion at one position, so the
+// field does not depend on them; the only shared data are the charge arrays,
+// which the particle half adds the products' charge to -- after the field
+// half has loaded them: the field workgroup posts the step index + 1 in
+// Counters::field_loaded once every thread holds its charges, and the
+// particle workgroup waits for that before its first deposit.  Workgroups are
+// dispatched in order and the field half never waits, so the wait ends.  The
+// pair sink removes victims' charge before the solve: both halves in one
+// workgroup then.
+constexpr int kRoleBoth = 0, kRoleField = 1, kRoleParticles = 2;
+constexpr uint32_t kLoadedSpinMax = 1u << 22;   // s_sleep rounds before giving up (about 0.2 s)
+
+__device__ __forceinline__ void post_field_loaded(const Params& P, int64_t step_in)
+{
+    __syncthreads();   // every thread of the field half holds its charges
+    if (threadIdx.x == 0)
+        __hip_atomic_store(&P.cnt->field_loaded, step_in + 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ __forceinline__ void wait_field_loaded(const Params& P, int64_t step_in)
+{
+    if (threadIdx.x == 0) {
+        for (uint32_t it = 0;; ++it) {
+            if (__hip_atomic_load(&P.cnt->field_loaded, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == step_in + 1)
+                break;
+            if (it == kLoadedSpinMax) {   // never expected: flag the step's field as suspect
+                set_err(P, kErrField);
+                break;
+            }
+            __builtin_amdgcn_s_sleep(4);
+        }
+    }
+    __syncthreads();
+}
+
 template <class St>
 __device__ __forceinline__ void finish_column(const Params& P, const St& se, const St& si, int64_t* rho_e,
-                                              int64_t* rho_i, int64_t* zero_a, int64_t* zero_b)
+                                              int64_t* rho_i, int64_t* zero_a, int64_t* zero_b, int role)
 {
+    const bool do_field = role != kRoleParticles;
+    const bool do_parts = role != kRoleField;
     __shared__ uint32_t sPid[kListMax];
     __shared__ uint32_t sFlag[2][kListMax / 32];
     __shared__ uint32_t sUpd[kOneBlock / 32];
@@ -1370,7 +1410,8 @@ __device__ __forceinline__ void finish_column(const Params& P, const St& se, con
     const int64_t nb_in = cnt->nb;
     const int64_t step_in = cnt->step;
     FieldPre fp;
-    if (P.poisson && !P.pair) fp = field_prepare(P, field_load(P, rho_e, rho_i));
+    if (do_field && P.poisson && !P.pair) fp = field_prepare(P, field_load(P, rho_e, rho_i));
+    if (role == kRoleField) post_field_loaded(P, step_in);
     int64_t nb = nb_in < P.max_births ? nb_in : P.max_births;
     int64_t nh[2], Np[2];
     bool lds[2];
@@ -1396,22 +1437,22 @@ __device__ __forceinline__ void finish_column(const Params& P, const St& se, con
     const bool bfast = nb <= int64_t(kBirthRegs) * T;   // every birth held in registers
     // (unconditional loads from clamped, always valid slots: no branch or
     // merge makes the thread wait for them before the field solve)
-    int64_t myh[2];
+    int64_t myh[2] = {0, 0};
     PartRegs<St> tail[2];
-    for (int s = 0; s < 2; ++s) {
-        const bool own = tid < nh[s];
-        myh[s] = P.holes[s][own ? tid : 0];
-        tail[s] = load_part(s == 0 ? se : si, uint32_t(own ? Np[s] + tid : 0));
-    }
     Birth b0;
-    {
+    if (do_parts) {
+        for (int s = 0; s < 2; ++s) {
+            const bool own = tid < nh[s];
+            myh[s] = P.holes[s][own ? tid : 0];
+            tail[s] = load_part(s == 0 ? se : si, uint32_t(own ? Np[s] + tid : 0));
+        }
         const int64_t k = tid < nb ? tid : 0;
         b0.pid = P.births[k].pid;
         b0.slot = P.births[k].slot;
         b0.x = P.births[k].x;
         b0.eps = P.births[k].eps;
     }
-    if (hfast) {
+    if (hfast && do_parts) {
         for (int k = tid; k < 2 * (kListMax / 32); k += T) (&sFlag[0][0])[k] = 0u;
         for (int k = tid; k < kOneBlock / 32; k += T) sUpd[k] = 0u;
     }
@@ -1428,7 +1469,7 @@ __device__ __forceinline__ void finish_column(const Params& P, const St& se, con
     //    gap, backward Euler: V' (1 + a) = V_source + R J + a V, a = R eps0/(L dt)
     double Vf = P.V, Jc = 0.0;
     int64_t vi = 0;
-    if (P.circuit) {
+    if (P.circuit && do_field) {
         __shared__ int64_t sCur[2];
         static_assert(kCurSlots == 64, "one slot per lane of wave 0");
         if (tid < 64) {   // wave 0 adds the slots up
@@ -1450,9 +1491,9 @@ __device__ __forceinline__ void finish_column(const Params& P, const St& se, con
     //    step's products: the solve needs only the charges deposited by the
     //    advance kernels and runs first.
     //    FP32 particles also get the field scaled to cells per step^2.
-    if (P.poisson) {
+    if (do_field && P.poisson) {
         field_solve(P, fp, P.E, nullptr, true, P.Ef_e != nullptr, Vf);
-    } else {
+    } else if (do_field) {
         const double e0 = P.periodic ? -P.E0 : -(Vf / P.L);
         for (int j = tid; j <= P.nn; j += T) {
             P.E[j] = e0;
@@ -1461,14 +1502,33 @@ __device__ __forceinline__ void finish_column(const Params& P, const St& se, con
                 P.Ef_i[j] = float(e0 * P.efs_i);
             }
         }
-        __syncthreads();   // (the solve's own barrier orders the LDS clears above)
     }
+    if (role == kRoleField) {
+        // the circuit state of this solve; the next charge buffers and the
+        // current slots cleared for the next step
+        if (tid == 0 && P.circuit) {
+            cnt->V = Vf;
+            cnt->J = Jc;
+            if (step_in % P.ion_subcycle == 0) cnt->vsum_i = vi;
+        }
+        for (int j = tid; j < P.nn; j += T) {
+            if (zero_a) zero_a[j] = 0;
+            if (zero_b) zero_b[j] = 0;
+        }
+        if (P.circuit && tid < kCurSlots) {
+            P.csum[tid] = 0;
+            if (step_in % P.ion_subcycle == 0) P.csum[kCurSlots + tid] = 0;
+        }
+        return;
+    }
+    __syncthreads();   // (orders the LDS clears above against their use)
     const uint32_t step = uint32_t(step_in);
 
     // 2. births: parent update, products' charge; product velocities kept in
     //    registers (lists longer than kListMax recompute them in step 3)
     double bve[kBirthRegs][3], bvi[kBirthRegs][3], bx[kBirthRegs];
     uint32_t bpid[kBirthRegs];
+    bool waited = false;   // particle half: the field half's charges are loaded
 #pragma unroll
     for (int m = 0; m < kBirthRegs; ++m) {
         bpid[m] = 0;
@@ -1487,14 +1547,29 @@ __device__ __forceinline__ void finish_column(const Params& P, const St& se, con
                 // a parent in the tail: its mover reads the new velocity back
                 if (hfast && b.slot >= Np[0] && b.slot < Np[0] + nh[0])
                     atomicOr(&sUpd[(b.slot - Np[0]) >> 5], 1u << ((b.slot - Np[0]) & 31));
-                deposit_global(P, se, rho_e, b.x);
-                deposit_global(P, si, rho_i, b.x);
                 sPid[k] = b.pid;
                 bpid[m] = b.pid;
                 bx[m] = b.x;
             }
         }
+        // the products' charge, once the field half holds this step's charges
+        if (role == kRoleParticles && nb > 0) {
+            wait_field_loaded(P, step_in);
+            waited = true;
+        }
+#pragma unroll
+        for (int m = 0; m < kBirthRegs; ++m) {
+            const int64_t k = tid + int64_t(m) * T;
+            if (k < nb) {
+                deposit_global(P, se, rho_e, bx[m]);
+                deposit_global(P, si, rho_i, bx[m]);
+            }
+        }
     } else {
+        if (role == kRoleParticles && nb > 0) {
+            wait_field_loaded(P, step_in);
+            waited = true;
+        }
         for (int64_t k = tid; k < nb; k += T) {
             const Birth b = P.births[k];
             double vs[3], ve[3], vi[3];
@@ -1641,7 +1716,10 @@ __device__ __forceinline__ void finish_column(const Params& P, const St& se, con
         put_particle(P, se, Np[0] + grow + r, kElectron, key_of_x(P, se, x), v, id);
     }
     // 5. counters (no other thread of this kernel reads them) and clearing of
-    //    the next charge buffers; nothing here waits for the particle stores
+    //    the next charge buffers; nothing here waits for the particle stores.
+    //    The particle half writes the step index only after the field half
+    //    has read it (and every other counter it reads).
+    if (role == kRoleParticles && !waited) wait_field_loaded(P, step_in);
     if (tid == 0) {
         cnt->n[0] = Np[0] + grow + n_emit;
         cnt->n[1] = Np[1] + grow;
@@ -1649,7 +1727,7 @@ __device__ __forceinline__ void finish_column(const Params& P, const St& se, con
         cnt->next_id[1] = id_in[1] + grow;
         if (id_in[0] + grow + n_emit > 0xFFFFFFFFll || id_in[1] + grow > 0xFFFFFFFFll) set_err(P, kErrIds);
         if (P.emit) cnt->carry = ce - double(n_emit);
-        if (P.circuit) {
+        if (P.circuit && role == kRoleBoth) {
             cnt->V = Vf;
             cnt->J = Jc;
             if (step_in % P.ion_subcycle == 0) cnt->vsum_i = vi;
@@ -1664,14 +1742,16 @@ __device__ __forceinline__ void finish_column(const Params& P, const St& se, con
         cnt->nh[1] = 0;
         cnt->step = step_in + 1;
     }
-    for (int j = tid; j < P.nn; j += T) {
-        if (zero_a) zero_a[j] = 0;
-        if (zero_b) zero_b[j] = 0;
-    }
-    // the current slots start the next step at zero (the ions' on their steps)
-    if (P.circuit && tid < kCurSlots) {
-        P.csum[tid] = 0;
-        if (step_in % P.ion_subcycle == 0) P.csum[kCurSlots + tid] = 0;
+    if (role == kRoleBoth) {
+        for (int j = tid; j < P.nn; j += T) {
+            if (zero_a) zero_a[j] = 0;
+            if (zero_b) zero_b[j] = 0;
+        }
+        // the current slots start the next step at zero (the ions' on their steps)
+        if (P.circuit && tid < kCurSlots) {
+            P.csum[tid] = 0;
+            if (step_in % P.ion_subcycle == 0) P.csum[kCurSlots + tid] = 0;
+        }
     }
 }
 
@@ -2050,7 +2130,8 @@ template <class St, int Threads>
 __global__ __launch_bounds__(Threads) void k_finish(Params P, St se, St si, int64_t* rho_e, int64_t* rho_i,
                                                     int64_t* zero_a, int64_t* zero_b)
 {
-    finish_column(P, se, si, rho_e, rho_i, zero_a, zero_b);
+    finish_column(P, se, si, rho_e, rho_i, zero_a, zero_b,
+                  P.pair ? kRoleBoth : (blockIdx.x == 0 ? kRoleField : kRoleParticles));
 }
 template <class St>
 __global__ __launch_bounds__(256) void k_sort_count(Params P, St sp, int S)
@@ -2100,10 +2181,12 @@ __global__ __launch_bounds__(kAdvBlock) void k_batch_advance_i(const ColumnDev* 
 template <class St>
 __global__ __launch_bounds__(kOneBlock) void k_batch_finish(const ColumnDev* __restrict__ cols, BatchStep b)
 {
-    const ColumnDev& C = cols[blockIdx.x];
+    // two workgroups per column (field half, then particle half)
+    const ColumnDev& C = cols[blockIdx.x >> 1];
     finish_column(C.P, store_of<St>(C, kElectron, b.cur[kElectron]), store_of<St>(C, kIon, b.cur[kIon]),
                   C.rho[kElectron][b.re_new], C.rho[kIon][b.ri_use], C.rho[kElectron][b.re_old],
-                  b.ri_old >= 0 ? C.rho[kIon][b.ri_old] : nullptr);
+                  b.ri_old >= 0 ? C.rho[kIon][b.ri_old] : nullptr,
+                  (blockIdx.x & 1) == 0 ? kRoleField : kRoleParticles);
 }
 template <class St>
 __global__ __launch_bounds__(256) void k_batch_sort_count(const ColumnDev* __restrict__ cols,
@@ -2184,12 +2267,14 @@ static hipError_t finish_t(const Params& P, const St& se, const St& si, int64_t*
     // waves leave too few lanes for the birth and hole lists (measured on a
     // 2000-cell column: 512 threads 27.8, 256 threads 28.5, 1024 threads
     // 28.8 microseconds per step)
+    // two workgroups (field half, particle half) except with the pair sink
+    const dim3 g(P.pair ? 1 : 2);
     if (P.nn <= 512 * kMaxSeg)
-        hipLaunchKernelGGL((k_finish<St, 512>), dim3(1), dim3(512), 0, st, P, se, si, rho_e, rho_i, zero_a, zero_b);
+        hipLaunchKernelGGL((k_finish<St, 512>), g, dim3(512), 0, st, P, se, si, rho_e, rho_i, zero_a, zero_b);
     else if (P.nn <= 768 * kMaxSeg)
-        hipLaunchKernelGGL((k_finish<St, 768>), dim3(1), dim3(768), 0, st, P, se, si, rho_e, rho_i, zero_a, zero_b);
+        hipLaunchKernelGGL((k_finish<St, 768>), g, dim3(768), 0, st, P, se, si, rho_e, rho_i, zero_a, zero_b);
     else
-        hipLaunchKernelGGL((k_finish<St, kOneBlock>), dim3(1), dim3(kOneBlock), 0, st, P, se, si, rho_e, rho_i,
+        hipLaunchKernelGGL((k_finish<St, kOneBlock>), g, dim3(kOneBlock), 0, st, P, se, si, rho_e, rho_i,
                            zero_a, zero_b);
     return hipGetLastError();
 }
@@ -2233,8 +2318,8 @@ hipError_t batch_advance_i(const ColumnDev* cols, int fp32, const BatchItem* ite
 }
 hipError_t batch_finish(const ColumnDev* cols, int n_cols, int fp32, const BatchStep& b, hipStream_t st)
 {
-    if (fp32) hipLaunchKernelGGL(k_batch_finish<Soa32>, dim3(n_cols), dim3(kOneBlock), 0, st, cols, b);
-    else hipLaunchKernelGGL(k_batch_finish<Soa>, dim3(n_cols), dim3(kOneBlock), 0, st, cols, b);
+    if (fp32) hipLaunchKernelGGL(k_batch_finish<Soa32>, dim3(2 * n_cols), dim3(kOneBlock), 0, st, cols, b);
+    else hipLaunchKernelGGL(k_batch_finish<Soa>, dim3(2 * n_cols), dim3(kOneBlock), 0, st, cols, b);
     return hipGetLastError();
 }
 template <class St>
