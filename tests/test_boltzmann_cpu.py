@@ -90,3 +90,20 @@ def test_oracle_swarm_matches_two_term():
     assert o.errors == 0
     assert abs(w / s.w - 1) < 0.03
     assert abs(np.mean(es) / s.eps_mean - 1) < 0.03
+
+
+@pytest.mark.parametrize("p_torr, frozen", [(1.0, W.NU_W_NE_1TORR_10VCM), (0.5, W.NU_W_NE_05TORR_10VCM)])
+def test_workload_wall_frequency_is_eq2(p_torr, frozen):
+    # eq. (2): nu_w = (2.405 / R)^2 D_a with D_a = mu_i D_e / mu_e (the
+    # ambipolar diffusion of section II), R = 1 cm, mu_i N = 4e21 /(V m s),
+    # D_e / mu_e from the two-term solution at E0 = 10 V/cm: the value the
+    # neon workloads freeze in their configs
+    cfg = W.with_(W.column_20cm(), p_torr=p_torr)
+    N = p_torr * (101325.0 / 760.0) / (B.KB * cfg["Tg"])
+    s = B.solve(cfg, 1000.0 / N)
+    Da = 4.0e21 / N * s.DN / s.muN
+    nu = (2.405 / 0.01) ** 2 * Da
+    assert abs(nu / frozen - 1) < 0.01, (nu, frozen)
+    for wl in (W.small_bounded(), W.column_20cm(), W.column_50cm()):
+        if wl["p_torr"] == p_torr:
+            assert wl["nu_w"] == frozen
