@@ -199,15 +199,15 @@ Layout layout(const Derived& d)
         return at;
     };
     L.counters = take(sizeof(Counters));
-    // FP64: x, vx, vy, vz (8 B) + id; FP32: cell, offset, vx, vy, vz (4 B) + id
+    // FP64: x, vx (8 B), (vy, vz) (16 B), id (4 B); FP32: cell, offset, vx (4 B), (vy, vz) (8 B), id
     for (int s = 0; s < 2; ++s)
         for (int b = 0; b < 2; ++b) {
-            if (d.fp32) {
-                for (int f = 0; f < 6; ++f) L.soa[s][b][f] = take(d.cap * 4);
-            } else {
-                for (int f = 0; f < 4; ++f) L.soa[s][b][f] = take(d.cap * 8);
-                L.soa[s][b][4] = take(d.cap * 4);
-            }
+            const int64_t w = d.fp32 ? 4 : 8;
+            L.soa[s][b][0] = take(d.cap * w);
+            L.soa[s][b][1] = take(d.cap * w);
+            L.soa[s][b][2] = take(d.cap * 2 * w);
+            L.soa[s][b][3] = take(d.cap * 4);
+            if (d.fp32) L.soa[s][b][4] = take(d.cap * 4);
         }
     for (int s = 0; s < 2; ++s)
         for (int b = 0; b < 2; ++b) L.rho[s][b] = take(int64_t(d.nn) * 8);
@@ -360,17 +360,15 @@ static pc_status column_init(const pc_config* cfg, const Derived& d, char* base,
                 Soa32& q = h->buf32[sp][b];
                 q.cell = reinterpret_cast<int32_t*>(base + L.soa[sp][b][0]);
                 q.off = reinterpret_cast<float*>(base + L.soa[sp][b][1]);
-                q.vx = reinterpret_cast<float*>(base + L.soa[sp][b][2]);
-                q.vy = reinterpret_cast<float*>(base + L.soa[sp][b][3]);
-                q.vz = reinterpret_cast<float*>(base + L.soa[sp][b][4]);
-                q.id = reinterpret_cast<uint32_t*>(base + L.soa[sp][b][5]);
+                q.vt = reinterpret_cast<float2*>(base + L.soa[sp][b][2]);
+                q.id = reinterpret_cast<uint32_t*>(base + L.soa[sp][b][3]);
+                q.vx = reinterpret_cast<float*>(base + L.soa[sp][b][4]);
             } else {
                 Soa& q = h->buf[sp][b];
                 q.x = reinterpret_cast<double*>(base + L.soa[sp][b][0]);
                 q.vx = reinterpret_cast<double*>(base + L.soa[sp][b][1]);
-                q.vy = reinterpret_cast<double*>(base + L.soa[sp][b][2]);
-                q.vz = reinterpret_cast<double*>(base + L.soa[sp][b][3]);
-                q.id = reinterpret_cast<uint32_t*>(base + L.soa[sp][b][4]);
+                q.vt = reinterpret_cast<double2*>(base + L.soa[sp][b][2]);
+                q.id = reinterpret_cast<uint32_t*>(base + L.soa[sp][b][3]);
             }
             h->rho[sp][b] = reinterpret_cast<int64_t*>(base + L.rho[sp][b]);
         }
@@ -808,15 +806,14 @@ pc_status pc_get_state(pc_handle h, int32_t species, double* x, double* vx, doub
     const int64_t n = std::min<int64_t>(cap, h->host_cnt.n[species]);
     if (n == 0) return PC_OK;
     if (h->fp32) {
-        const Soa dst{x, vx, vy, vz, id};
+        const pcdev::SoaIO dst{x, vx, vy, vz, id};
         HIPCHK(pclaunch::to64(h->P, h->buf32[species][h->cur[species]], dst, n, species, h->st));
         return PC_OK;
     }
     const Soa q = soa_of(h, species);
     if (x) HIPCHK(hipMemcpyAsync(x, q.x, n * 8, hipMemcpyDeviceToDevice, h->st));
     if (vx) HIPCHK(hipMemcpyAsync(vx, q.vx, n * 8, hipMemcpyDeviceToDevice, h->st));
-    if (vy) HIPCHK(hipMemcpyAsync(vy, q.vy, n * 8, hipMemcpyDeviceToDevice, h->st));
-    if (vz) HIPCHK(hipMemcpyAsync(vz, q.vz, n * 8, hipMemcpyDeviceToDevice, h->st));
+    HIPCHK(pclaunch::vt_split(q.vt, vy, vz, n, h->st));
     if (id) HIPCHK(hipMemcpyAsync(id, q.id, n * 4, hipMemcpyDeviceToDevice, h->st));
     return PC_OK;
 }
@@ -833,8 +830,7 @@ pc_status pc_set_state(pc_handle h, int32_t species, int64_t n, const double* x,
     if (!h->fp32 && n > 0) {
         HIPCHK(hipMemcpyAsync(q.x, x, n * 8, hipMemcpyDeviceToDevice, h->st));
         HIPCHK(hipMemcpyAsync(q.vx, vx, n * 8, hipMemcpyDeviceToDevice, h->st));
-        HIPCHK(hipMemcpyAsync(q.vy, vy, n * 8, hipMemcpyDeviceToDevice, h->st));
-        HIPCHK(hipMemcpyAsync(q.vz, vz, n * 8, hipMemcpyDeviceToDevice, h->st));
+        HIPCHK(pclaunch::vt_join(vy, vz, q.vt, n, h->st));
         HIPCHK(hipMemcpyAsync(q.id, id, n * 4, hipMemcpyDeviceToDevice, h->st));
     }
     h->host_cnt.n[species] = n;
@@ -846,8 +842,8 @@ pc_status pc_set_state(pc_handle h, int32_t species, int64_t n, const double* x,
     // positions must lie in [0, L): checked by a deposit into scratch charge
     // (the FP32 conversion checks them itself)
     if (n > 0 && h->fp32) {
-        const Soa src{const_cast<double*>(x), const_cast<double*>(vx), const_cast<double*>(vy),
-                      const_cast<double*>(vz), const_cast<uint32_t*>(id)};
+        const pcdev::SoaIO src{const_cast<double*>(x), const_cast<double*>(vx), const_cast<double*>(vy),
+                               const_cast<double*>(vz), const_cast<uint32_t*>(id)};
         HIPCHK(pclaunch::from64(h->P, src, h->buf32[species][h->cur[species]], n, species, h->st));
     } else if (n > 0) {
         int64_t* scratch = h->rho[0][1 - h->re_cur];   // the next electron charge buffer: zero and unused

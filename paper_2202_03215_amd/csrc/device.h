@@ -66,11 +66,14 @@ struct Birth {           // one ionization event (56 bytes)
     double pad;
 };
 
-struct Soa {             // one structure-of-arrays particle buffer (FP64)
+// One particle buffer (FP64): x and vx are read and written by every push, the
+// transverse velocity (vy, vz) only by the few collision candidates of a step,
+// so the pair is interleaved: a candidate touches one 16-byte element (one
+// cache line) instead of two lines of two arrays.
+struct Soa {
     double* x;
     double* vx;
-    double* vy;
-    double* vz;
+    double2* vt;         // (vy, vz)
     uint32_t* id;
 };
 
@@ -80,8 +83,17 @@ struct Soa32 {
     int32_t* cell;
     float* off;
     float* vx;
-    float* vy;
-    float* vz;
+    float2* vt;          // (vy, vz)
+    uint32_t* id;
+};
+
+// Caller-side FP64 arrays (state exchange through the C ABI): separate
+// vy and vz; any pointer may be null where documented.
+struct SoaIO {
+    double* x;
+    double* vx;
+    double* vy;
+    double* vz;
     uint32_t* id;
 };
 

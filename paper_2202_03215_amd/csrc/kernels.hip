@@ -203,31 +203,31 @@ __device__ __forceinline__ void load_v(const Params&, const Soa& s, uint32_t i, 
                                        double& vz)
 {
     vx = s.vx[i];
-    vy = s.vy[i];
-    vz = s.vz[i];
+    const double2 t = s.vt[i];
+    vy = t.x;
+    vz = t.y;
 }
 __device__ __forceinline__ void load_v(const Params& P, const Soa32& s, uint32_t i, int sp, double& vx,
                                        double& vy, double& vz)
 {
     const double k = sp == kElectron ? P.u2v_e : P.u2v_i;
     vx = double(s.vx[i]) * k;
-    vy = double(s.vy[i]) * k;
-    vz = double(s.vz[i]) * k;
+    const float2 t = s.vt[i];
+    vy = double(t.x) * k;
+    vz = double(t.y) * k;
 }
 __device__ __forceinline__ void store_v(const Params&, const Soa& s, uint32_t i, int, double vx, double vy,
                                         double vz)
 {
     s.vx[i] = vx;
-    s.vy[i] = vy;
-    s.vz[i] = vz;
+    s.vt[i] = make_double2(vy, vz);
 }
 __device__ __forceinline__ void store_v(const Params& P, const Soa32& s, uint32_t i, int sp, double vx,
                                         double vy, double vz)
 {
     const double k = sp == kElectron ? P.u2v_e : P.u2v_i;
     s.vx[i] = float(vx / k);
-    s.vy[i] = float(vy / k);
-    s.vz[i] = float(vz / k);
+    s.vt[i] = make_float2(float(vy / k), float(vz / k));
 }
 // position key of a position x [m] for put_particle: x itself (FP64) or x / dx (FP32)
 __device__ __forceinline__ double key_of_x(const Params&, const Soa&, double x) { return x; }
@@ -258,8 +258,7 @@ __device__ __forceinline__ void move_particle(const Soa& sp, uint32_t dst, uint3
 {
     sp.x[dst] = sp.x[src];
     sp.vx[dst] = sp.vx[src];
-    sp.vy[dst] = sp.vy[src];
-    sp.vz[dst] = sp.vz[src];
+    sp.vt[dst] = sp.vt[src];
     sp.id[dst] = sp.id[src];
 }
 __device__ __forceinline__ void move_particle(const Soa32& sp, uint32_t dst, uint32_t src)
@@ -267,35 +266,35 @@ __device__ __forceinline__ void move_particle(const Soa32& sp, uint32_t dst, uin
     sp.cell[dst] = sp.cell[src];
     sp.off[dst] = sp.off[src];
     sp.vx[dst] = sp.vx[src];
-    sp.vy[dst] = sp.vy[src];
-    sp.vz[dst] = sp.vz[src];
+    sp.vt[dst] = sp.vt[src];
     sp.id[dst] = sp.id[src];
 }
 // one particle held in registers (the finish kernel's tail prefetch)
 template <class St> struct PartRegs;
 template <> struct PartRegs<Soa> {
-    double x, vx, vy, vz;
+    double x, vx;
+    double2 vt;
     uint32_t id;
 };
 template <> struct PartRegs<Soa32> {
     int32_t cell;
-    float off, vx, vy, vz;
+    float off, vx;
+    float2 vt;
     uint32_t id;
 };
 __device__ __forceinline__ PartRegs<Soa> load_part(const Soa& sp, uint32_t i)
 {
-    return PartRegs<Soa>{sp.x[i], sp.vx[i], sp.vy[i], sp.vz[i], sp.id[i]};
+    return PartRegs<Soa>{sp.x[i], sp.vx[i], sp.vt[i], sp.id[i]};
 }
 __device__ __forceinline__ PartRegs<Soa32> load_part(const Soa32& sp, uint32_t i)
 {
-    return PartRegs<Soa32>{sp.cell[i], sp.off[i], sp.vx[i], sp.vy[i], sp.vz[i], sp.id[i]};
+    return PartRegs<Soa32>{sp.cell[i], sp.off[i], sp.vx[i], sp.vt[i], sp.id[i]};
 }
 __device__ __forceinline__ void store_part(const Soa& sp, uint32_t i, const PartRegs<Soa>& r)
 {
     sp.x[i] = r.x;
     sp.vx[i] = r.vx;
-    sp.vy[i] = r.vy;
-    sp.vz[i] = r.vz;
+    sp.vt[i] = r.vt;
     sp.id[i] = r.id;
 }
 __device__ __forceinline__ void store_part(const Soa32& sp, uint32_t i, const PartRegs<Soa32>& r)
@@ -303,8 +302,7 @@ __device__ __forceinline__ void store_part(const Soa32& sp, uint32_t i, const Pa
     sp.cell[i] = r.cell;
     sp.off[i] = r.off;
     sp.vx[i] = r.vx;
-    sp.vy[i] = r.vy;
-    sp.vz[i] = r.vz;
+    sp.vt[i] = r.vt;
     sp.id[i] = r.id;
 }
 // write a new particle at slot p from a position key and a velocity [m/s]
@@ -313,8 +311,7 @@ __device__ __forceinline__ void put_particle(const Params& P, const Soa& s, int6
 {
     s.x[p] = xk;
     s.vx[p] = v[0];
-    s.vy[p] = v[1];
-    s.vz[p] = v[2];
+    s.vt[p] = make_double2(v[1], v[2]);
     s.id[p] = id;
 }
 __device__ __forceinline__ void put_particle(const Params& P, const Soa32& s, int64_t p, int sp, double xk,
@@ -339,8 +336,7 @@ __device__ __forceinline__ void copy_particle(const Soa& d, int64_t p, const Soa
 {
     d.x[p] = s.x[i];
     d.vx[p] = s.vx[i];
-    d.vy[p] = s.vy[i];
-    d.vz[p] = s.vz[i];
+    d.vt[p] = s.vt[i];
     d.id[p] = s.id[i];
 }
 __device__ __forceinline__ void copy_particle(const Soa32& d, int64_t p, const Soa32& s, int64_t i)
@@ -348,8 +344,7 @@ __device__ __forceinline__ void copy_particle(const Soa32& d, int64_t p, const S
     d.cell[p] = s.cell[i];
     d.off[p] = s.off[i];
     d.vx[p] = s.vx[i];
-    d.vy[p] = s.vy[i];
-    d.vz[p] = s.vz[i];
+    d.vt[p] = s.vt[i];
     d.id[p] = s.id[i];
 }
 
@@ -606,7 +601,8 @@ __device__ __forceinline__ void advance_i_chunk(const Params& P, const Soa& sp, 
                     alive = false;
                     code = kEvWall;
                 } else if (k0 < P.kcx) {
-                    double vy = sp.vy[i], vz = sp.vz[i];
+                    const double2 vt = sp.vt[i];
+                    const double vy = vt.x, vz = vt.y;
                     WordStream ws(id, step, kStreamIonStep, P.key0, P.key1);
                     double g0, g1, g2;
                     normal3(ws, g0, g1, g2);
@@ -617,13 +613,10 @@ __device__ __forceinline__ void advance_i_chunk(const Params& P, const Soa& sp, 
                     if (u1 * P.g_cap < g) {
                         code = kEvCX;
                         vx = ax;
-                        vy = ay;
-                        vz = az;
+                        sp.vt[i] = make_double2(ay, az);
                     } else {
                         code = kEvNull;
                     }
-                    sp.vy[i] = vy;
-                    sp.vz[i] = vz;
                 }
             }
             if (alive) {
@@ -851,8 +844,9 @@ __device__ __forceinline__ void advance_i_chunk(const Params& P, const Soa32& sp
                 } else if (k0 < P.kcx) {
                     const double u1 = unif52(w.c, w.d);
                     const double vx = double(u) * P.u2v_i;
-                    const double vy = double(sp.vy[i]) * P.u2v_i;
-                    const double vz = double(sp.vz[i]) * P.u2v_i;
+                    const float2 vt = sp.vt[i];
+                    const double vy = double(vt.x) * P.u2v_i;
+                    const double vz = double(vt.y) * P.u2v_i;
                     WordStream ws(id, step, kStreamIonStep, P.key0, P.key1);
                     double g0, g1, g2;
                     normal3(ws, g0, g1, g2);
@@ -863,8 +857,7 @@ __device__ __forceinline__ void advance_i_chunk(const Params& P, const Soa32& sp
                     if (u1 * P.g_cap < g) {
                         code = kEvCX;
                         u = float(ax / P.u2v_i);
-                        sp.vy[i] = float(ay / P.u2v_i);
-                        sp.vz[i] = float(az / P.u2v_i);
+                        sp.vt[i] = make_float2(float(ay / P.u2v_i), float(az / P.u2v_i));
                     } else {
                         code = kEvNull;
                     }
@@ -932,8 +925,7 @@ __global__ __launch_bounds__(256) void k_load32(Params P, Soa32 sp, int64_t n0, 
     sp.cell[k] = c;
     sp.off[k] = off;
     sp.vx[k] = ux;
-    sp.vy[k] = uy;
-    sp.vz[k] = uz;
+    sp.vt[k] = make_float2(uy, uz);
     sp.id[k] = uint32_t(k);
 }
 
@@ -950,19 +942,22 @@ __global__ __launch_bounds__(256) void k_halfstep32(Params P, Soa32 sp, int64_t 
 }
 
 // x = (cell + off) dx, v = u dx/dt (caller arrays; any may be null)
-__global__ __launch_bounds__(256) void k_to64(Params P, Soa32 src, Soa dst, int64_t n, int S)
+__global__ __launch_bounds__(256) void k_to64(Params P, Soa32 src, SoaIO dst, int64_t n, int S)
 {
     const int64_t k = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
     if (k >= n) return;
     const double u2v = S == kElectron ? P.u2v_e : P.u2v_i;
     if (dst.x) dst.x[k] = (double(src.cell[k]) + double(src.off[k])) * P.dx;
     if (dst.vx) dst.vx[k] = double(src.vx[k]) * u2v;
-    if (dst.vy) dst.vy[k] = double(src.vy[k]) * u2v;
-    if (dst.vz) dst.vz[k] = double(src.vz[k]) * u2v;
+    if (dst.vy || dst.vz) {
+        const float2 t = src.vt[k];
+        if (dst.vy) dst.vy[k] = double(t.x) * u2v;
+        if (dst.vz) dst.vz[k] = double(t.y) * u2v;
+    }
     if (dst.id) dst.id[k] = src.id[k];
 }
 
-__global__ __launch_bounds__(256) void k_from64(Params P, Soa src, Soa32 dst, int64_t n, int S)
+__global__ __launch_bounds__(256) void k_from64(Params P, SoaIO src, Soa32 dst, int64_t n, int S)
 {
     const int64_t k = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
     if (k >= n) return;
@@ -975,8 +970,7 @@ __global__ __launch_bounds__(256) void k_from64(Params P, Soa src, Soa32 dst, in
     dst.cell[k] = c;
     dst.off[k] = off;
     dst.vx[k] = ux;
-    dst.vy[k] = uy;
-    dst.vz[k] = uz;
+    dst.vt[k] = make_float2(uy, uz);
     dst.id[k] = src.id[k];
 }
 
@@ -1771,8 +1765,7 @@ __global__ __launch_bounds__(256) void k_load(Params P, Soa sp, int64_t n0, doub
     normal3(ws, g0, g1, g2);
     sp.x[k] = x;
     sp.vx[k] = sig * g0;
-    sp.vy[k] = sig * g1;
-    sp.vz[k] = sig * g2;
+    sp.vt[k] = make_double2(sig * g1, sig * g2);
     sp.id[k] = uint32_t(k);
 }
 
@@ -1865,14 +1858,31 @@ __global__ __launch_bounds__(kAdvBlock) void k_stream_copy(const double* __restr
     for (; i < ue; i += kAdvBlock) st32(dst, i, ld32(src, i));
 }
 
+// caller arrays <-> the interleaved transverse velocity of an FP64 store
+__global__ __launch_bounds__(256) void k_vt_split(const double2* __restrict__ vt, double* __restrict__ vy,
+                                                  double* __restrict__ vz, int64_t n)
+{
+    const int64_t k = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (k >= n) return;
+    const double2 t = vt[k];
+    if (vy) vy[k] = t.x;
+    if (vz) vz[k] = t.y;
+}
+__global__ __launch_bounds__(256) void k_vt_join(const double* __restrict__ vy, const double* __restrict__ vz,
+                                                 double2* __restrict__ vt, int64_t n)
+{
+    const int64_t k = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (k >= n) return;
+    vt[k] = make_double2(vy[k], vz[k]);
+}
+
 __global__ void k_copy_soa(Soa dst, Soa src, int64_t n)
 {
     const int64_t k = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
     if (k >= n) return;
     if (dst.x && src.x) dst.x[k] = src.x[k];
     if (dst.vx && src.vx) dst.vx[k] = src.vx[k];
-    if (dst.vy && src.vy) dst.vy[k] = src.vy[k];
-    if (dst.vz && src.vz) dst.vz[k] = src.vz[k];
+    if (dst.vt && src.vt) dst.vt[k] = src.vt[k];
     if (dst.id && src.id) dst.id[k] = src.id[k];
 }
 
@@ -2388,14 +2398,14 @@ hipError_t halfstep(const Params& P, const Soa32& sp, int species, int64_t n, hi
     return hipGetLastError();
 }
 
-hipError_t to64(const Params& P, const Soa32& src, const Soa& dst, int64_t n, int species, hipStream_t st)
+hipError_t to64(const Params& P, const Soa32& src, const SoaIO& dst, int64_t n, int species, hipStream_t st)
 {
     if (n == 0) return hipSuccess;
     hipLaunchKernelGGL(k_to64, dim3(grid_for(n, 256, 1 << 30)), dim3(256), 0, st, P, src, dst, n, species);
     return hipGetLastError();
 }
 
-hipError_t from64(const Params& P, const Soa& src, const Soa32& dst, int64_t n, int species, hipStream_t st)
+hipError_t from64(const Params& P, const SoaIO& src, const Soa32& dst, int64_t n, int species, hipStream_t st)
 {
     if (n == 0) return hipSuccess;
     hipLaunchKernelGGL(k_from64, dim3(grid_for(n, 256, 1 << 30)), dim3(256), 0, st, P, src, dst, n, species);
@@ -2444,6 +2454,19 @@ hipError_t stream_copy(const double* src, double* dst, int64_t n, int blocks, hi
 {
     if (n == 0) return hipSuccess;
     hipLaunchKernelGGL(k_stream_copy, dim3(blocks), dim3(kAdvBlock), 0, st, src, dst, n);
+    return hipGetLastError();
+}
+
+hipError_t vt_split(const double2* vt, double* vy, double* vz, int64_t n, hipStream_t st)
+{
+    if (n == 0 || (!vy && !vz)) return hipSuccess;
+    hipLaunchKernelGGL(k_vt_split, dim3(grid_for(n, 256, 1 << 30)), dim3(256), 0, st, vt, vy, vz, n);
+    return hipGetLastError();
+}
+hipError_t vt_join(const double* vy, const double* vz, double2* vt, int64_t n, hipStream_t st)
+{
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_vt_join, dim3(grid_for(n, 256, 1 << 30)), dim3(256), 0, st, vy, vz, vt, n);
     return hipGetLastError();
 }
 

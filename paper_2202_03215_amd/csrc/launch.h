@@ -6,6 +6,7 @@ namespace pclaunch {
 using pcdev::Params;
 using pcdev::Soa;
 using pcdev::Soa32;
+using pcdev::SoaIO;
 
 // t0/t1 (optional, both or neither): events that take the start and end
 // timestamps of the launch itself (hipExtLaunchKernelGGL), so that their
@@ -25,8 +26,10 @@ hipError_t load(const Params& P, int species, const Soa& sp, int64_t n0, double 
 hipError_t load(const Params& P, int species, const Soa32& sp, int64_t n0, double sig, hipStream_t st);
 hipError_t halfstep(const Params& P, const Soa& sp, int64_t n, double hq, hipStream_t st);
 hipError_t halfstep(const Params& P, const Soa32& sp, int species, int64_t n, hipStream_t st);
-hipError_t to64(const Params& P, const Soa32& src, const Soa& dst, int64_t n, int species, hipStream_t st);
-hipError_t from64(const Params& P, const Soa& src, const Soa32& dst, int64_t n, int species, hipStream_t st);
+hipError_t to64(const Params& P, const Soa32& src, const SoaIO& dst, int64_t n, int species, hipStream_t st);
+hipError_t from64(const Params& P, const SoaIO& src, const Soa32& dst, int64_t n, int species, hipStream_t st);
+hipError_t vt_split(const double2* vt, double* vy, double* vz, int64_t n, hipStream_t st);
+hipError_t vt_join(const double* vy, const double* vz, double2* vt, int64_t n, hipStream_t st);
 hipError_t fill_i64(int64_t* p, int64_t n, int64_t v, hipStream_t st);
 hipError_t deposit(const Params& P, const double* x, int64_t n, int64_t* rho, hipStream_t st);
 hipError_t deposit(const Params& P, const Soa32& sp, int64_t n, int64_t* rho, hipStream_t st);
