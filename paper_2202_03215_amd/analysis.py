@@ -107,3 +107,58 @@ def phase_velocity(snapshots: np.ndarray, times: np.ndarray, L: float, m: int | 
 def potential_drop_per_striation(E0: float, lam: float) -> float:
     """Eq. (1): the potential drop over one striation is E0 * lambda."""
     return E0 * lam
+
+
+def mode_amplitudes(coef: np.ndarray) -> np.ndarray:
+    """Relative amplitudes 2 |c_m| / c_0 of modes m >= 1 from Fourier
+    coefficients coef[t, m] of cell counts (c_0 = the total count)."""
+    c = np.asarray(coef)
+    return 2.0 * np.abs(c[:, 1:]) / c[:, 0].real[:, None]
+
+
+def striation_statistics(coef: np.ndarray, times: np.ndarray, L: float, t_from: float,
+                         lo: float = 1e-2, hi: float = 1e-1, onset: float = 0.1, nprof: int = 32) -> dict:
+    """Statistics of a free run from the Fourier coefficients coef[t, m]
+    (m = 0..M) of its electron cell counts at `times`:
+
+    - mode: the dominant mode over t >= t_from (largest mean amplitude),
+      wavelength L / mode (section III) and its mean relative amplitude
+      (modulation);
+    - first: the first mode whose amplitude exceeds `onset`, the onset time,
+      and its linear growth rate (slope of ln amplitude while it lies in
+      (lo, hi));
+    - phase velocity of the dominant mode over t >= t_from (negative: towards
+      the cathode, x = 0 being the cathode side of the imposed field);
+    - profile: the time-averaged density over one wavelength in the frame of
+      the wave (harmonics h * mode <= M, each rotated by h times the phase of
+      the dominant mode, averaged, summed), relative to the mean, on nprof
+      points."""
+    c = np.asarray(coef)
+    t = np.asarray(times, dtype=np.float64)
+    A = mode_amplitudes(c)
+    sel = t >= t_from
+    m = int(np.argmax(A[sel].mean(axis=0))) + 1
+    over = np.argwhere(A > onset)
+    first, t_on, growth = -1, float("nan"), float("nan")
+    if over.size:
+        k0 = over[0, 0]
+        cand = over[over[:, 0] == k0][:, 1]
+        first = int(cand[np.argmax(A[k0, cand])]) + 1
+        t_on = float(t[k0])
+        a = A[:, first - 1]
+        g = (a > lo) & (a < hi) & (t <= t_on)
+        if g.sum() >= 3:
+            growth = float(np.polyfit(t[g], np.log(a[g]), 1)[0])
+    k = 2.0 * np.pi * m / L
+    ph = np.unwrap(np.angle(c[sel, m]))
+    vph = float(-np.polyfit(t[sel], ph, 1)[0] / k)
+    M = c.shape[1] - 1
+    theta = np.angle(c[sel, m])
+    xs = (np.arange(nprof) + 0.5) / nprof
+    prof = np.zeros(nprof)
+    n0 = c[sel, 0].real.mean()
+    for h in range(1, M // m + 1):
+        ch = (c[sel, h * m] * np.exp(-1j * h * theta)).mean()
+        prof += 2.0 * np.real(ch * np.exp(2j * np.pi * h * xs)) / n0
+    return dict(mode=m, wavelength=L / m, modulation=float(A[sel, m - 1].mean()), first=first, onset=t_on,
+                growth=growth, phase_velocity=vph, profile=prof)

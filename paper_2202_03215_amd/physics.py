@@ -16,13 +16,15 @@ from . import analysis as A
 
 def run(cfg: dict, steps: int, every: int, eepf_from: int = 0, progress=None):
     """Returns dict(times [s], ne [snapshots, cells] (counts), eepf (summed
-    counts over snapshots at or after eepf_from steps), counts (n_e, n_i) per
-    snapshot)."""
+    counts over snapshots at or after eepf_from steps), energy_sum (their
+    summed energy moment, 2^-20 eV units) and energy_count (their summed
+    electron counts), counts (n_e, n_i) per snapshot)."""
     from .column import Column
     col = Column(cfg)
     nc = int(cfg["n_cells"])
     snaps, times, counts = [], [], []
     eepf = np.zeros(A.EEPF_BINS)
+    esum = ecount = 0
     done = 0
     while done < steps:
         k = min(every, steps - done)
@@ -36,10 +38,13 @@ def run(cfg: dict, steps: int, every: int, eepf_from: int = 0, progress=None):
         counts.append(c["n"])
         if done >= eepf_from:
             eepf += parts["eepf"][0]
+            esum += int(parts["eps"].sum())
+            ecount += int(parts["ne"].sum())
         if progress is not None:
             progress(done)
     col.sync()
-    return dict(times=np.array(times), ne=np.array(snaps), eepf=eepf, counts=np.array(counts))
+    return dict(times=np.array(times), ne=np.array(snaps), eepf=eepf, counts=np.array(counts),
+                energy_sum=esum, energy_count=ecount)
 
 
 def bounded_run(cfg: dict, steps: int, every: int, snap_every: int = 10, progress=None):

@@ -63,3 +63,34 @@ def field_close(Eg, Eo):
     Eg = np.asarray(Eg)
     Eo = np.asarray(Eo)
     return np.abs(Eg - Eo).max() <= TOL_E * np.abs(Eo).max()
+
+
+# ------------------------------------------- striated free runs (shared)
+_STRIATION_RUNS = {}
+
+
+def striation_config(column, seed, precision="fp64"):
+    """The striated neon columns of the long-run tests and of the oracle's
+    golden runs (1 Torr, periodic, E0 = 10 V/cm, balanced sink)."""
+    import workloads as W
+    s = {"4cm": dict(n_cells=400, L=0.04, ppc=100), "20cm": dict(n_cells=2000, L=0.20, ppc=200)}[column]
+    return W.with_(W.column_20cm(), n_cells=s["n_cells"], L=s["L"], V=s["L"] * 1000.0, ppc=s["ppc"],
+                   wall_mode="balanced", seed=seed, precision=precision)
+
+
+def striation_run(column, seed, precision, steps=200_000, every=None, modes=None):
+    """GPU free run of a striated column (2e5 steps), cached per process:
+    Fourier coefficients of the electron cell counts (modes 0..M) every
+    `every` steps, their times, the EEPF counts and energy sums over the
+    second half."""
+    from paper_2202_03215_amd import physics as PH
+    every = every or (1000 if column == "4cm" else 2000)
+    modes = modes or (32 if column == "4cm" else 64)
+    key = (column, seed, precision, steps, every, modes)
+    if key not in _STRIATION_RUNS:
+        cfg = striation_config(column, seed, precision)
+        r = PH.run(cfg, steps, every, eepf_from=steps // 2 + every)
+        coef = np.fft.rfft(r["ne"], axis=1)[:, :modes + 1]
+        _STRIATION_RUNS[key] = dict(coef=coef, times=r["times"], eepf=r["eepf"], energy_sum=r["energy_sum"],
+                                    energy_count=r["energy_count"], counts=r["counts"], cfg=cfg)
+    return _STRIATION_RUNS[key]
