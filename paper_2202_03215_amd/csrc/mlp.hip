@@ -95,16 +95,18 @@ __device__ __forceinline__ void layer64(const bf16 (*act)[K], const bf16 (*wt)[K
     }
 }
 
-// tanh for BF16 activations: sign(x) (1 - t)/(1 + t), t = 2^(-2|x| log2 e),
-// on the hardware exp2 and reciprocal; x itself below 2^-10 (error x^3/3).
-// Absolute error below 3e-7, far below the BF16 rounding that follows.
+// tanh for BF16 activations: 1 - 2 / (1 + e^(2x)), e^(2x) as 2^(2x log2 e) on
+// the hardware exp2, the quotient on its reciprocal, the last step one fused
+// multiply-add (exact at both ends: e^(2x) overflows to infinity for large x,
+// giving 1; underflows to 0 for very negative x, giving -1).  With exp2 and
+// the reciprocal each within one ulp, and r = 1/(1 + e) in (0, 1], the error
+// is at most 2 r (2^-23 + 2^-24 + 2^-23) + 2^-24 |tanh x| <= 6.6e-7 absolute
+// (3.6e-7 near zero, where r is 1/2); the subsequent BF16 rounding (2^-9
+// relative) dominates except within that distance of a rounding point.
 __device__ __forceinline__ float tanh_bf(float x)
 {
-    const float a = fabsf(x);
-    if (a < 0.0009765625f) return x;
-    const float t = __builtin_amdgcn_exp2f(-2.8853900817779268f * a);   // 2 log2(e)
-    const float r = (1.0f - t) * __builtin_amdgcn_rcpf(1.0f + t);
-    return copysignf(r, x);
+    const float e = __builtin_amdgcn_exp2f(2.8853900817779268f * x);   // 2 log2(e) x
+    return fmaf(-2.0f, __builtin_amdgcn_rcpf(1.0f + e), 1.0f);
 }
 
 // tanh of the accumulators (layer64's layout), rounded to BF16, into a
@@ -177,60 +179,95 @@ __device__ __forceinline__ void forward_tile(const PackedFwd& P, WaveLds& w, con
     out[0] = o;
 }
 
-// Inference needs each activation only for the next layer: two ping-pong
-// tiles instead of three, no gradient tile (5 KB per wave, so that 16 waves
-// of 512-thread blocks fit a compute unit with the staged weights).
+// Inference layout.  LDS rows of the weights and of the activation tile are
+// padded by 16 bytes: a 16x32 operand fragment is read by lanes l % 16 = row
+// at one column offset, and an unpadded row pitch of 64 or 128 bytes puts all
+// sixteen rows on the same banks; with a pitch of 80 or 144 bytes each group
+// of eight lanes covers all banks once.  Each wave keeps one activation tile:
+// a layer reads its inputs into registers before any of its outputs exist,
+// and the LDS operations of one wave complete in issue order.
 constexpr int kFwdBlock = 512;   // 8 waves
-struct alignas(16) FwdLds {
-    bf16 x[kTile][32];
-    bf16 ha[kTile][kH];
-    bf16 hb[kTile][kH];
+constexpr int kPad = 8;          // bf16 elements of row padding
+constexpr int kK1 = 32 + kPad, kK2 = kH + kPad;
+struct alignas(16) FwdParams {
+    bf16 w1t[kH][kK1];
+    bf16 w2t[kH][kK2];
+    bf16 w3t[kH][kK2];
+    bf16 w4t[16][kK2];
+    float b1[kH], b2[kH], b3[kH], b4[16];
 };
 
-// The 16 x 5 inputs of a tile are 80 consecutive floats: lanes l and l + 64
-// (< 80) load one each, a tile ahead of its use; the tile's padding columns
-// 5..31 are zeroed once per wave and never written again.
-struct XFetch {
-    float v0, v1;
-};
-__device__ __forceinline__ XFetch fetch_x(const float* __restrict__ x, int64_t s0, int64_t n)
+__device__ __forceinline__ void stage_fwd(FwdParams& s, const PackedFwd* __restrict__ g)
 {
-    const int l = lane();
-    const int64_t e = s0 * kIn, end = n * kIn;
-    XFetch f;
-    f.v0 = e + l < end ? x[e + l] : 0.0f;
-    f.v1 = (l < kTile * kIn - 64 && e + 64 + l < end) ? x[e + 64 + l] : 0.0f;
-    return f;
-}
-__device__ __forceinline__ void put_x(const XFetch& f, bf16 (*xs)[32])
-{
-    const int l = lane();
-    xs[l / kIn][l % kIn] = bf16(f.v0);
-    if (l < kTile * kIn - 64) xs[(64 + l) / kIn][(64 + l) % kIn] = bf16(f.v1);
+    for (int k = threadIdx.x; k < kH * 4; k += blockDim.x) {
+        const int r = k >> 2, c = (k & 3) * 8;
+        *reinterpret_cast<bf16x8*>(&s.w1t[r][c]) = ld8(&g->w1t[r][c]);
+    }
+    for (int k = threadIdx.x; k < kH * 8; k += blockDim.x) {
+        const int r = k >> 3, c = (k & 7) * 8;
+        *reinterpret_cast<bf16x8*>(&s.w2t[r][c]) = ld8(&g->w2t[r][c]);
+        *reinterpret_cast<bf16x8*>(&s.w3t[r][c]) = ld8(&g->w3t[r][c]);
+    }
+    for (int k = threadIdx.x; k < 16 * 8; k += blockDim.x) {
+        const int r = k >> 3, c = (k & 7) * 8;
+        *reinterpret_cast<bf16x8*>(&s.w4t[r][c]) = ld8(&g->w4t[r][c]);
+    }
+    for (int k = threadIdx.x; k < kH; k += blockDim.x) {
+        s.b1[k] = g->b1[k];
+        s.b2[k] = g->b2[k];
+        s.b3[k] = g->b3[k];
+    }
+    if (threadIdx.x < 16) s.b4[threadIdx.x] = g->b4[threadIdx.x];
 }
 
-__device__ __forceinline__ void forward_tile_inf(const PackedFwd& P, FwdLds& w, const XFetch& xf, int64_t s0,
-                                                 int64_t n, bf16* __restrict__ hidden, f32x4 out[1])
+// The first layer's B operand is x^T: lane l < 16 holds the five features of
+// sample l of the tile (K padded to 32 with zeros), the other lanes zeros, so
+// the inputs go from global memory straight into registers.  The loads are
+// unconditional (index clamped into the array, value zeroed outside it), so
+// that the next tile's loads stay in flight while this tile is computed.
+__device__ __forceinline__ void fetch_x(const float* __restrict__ x, int64_t s0, int64_t n, float v[kIn])
 {
-    f32x4 acc[4];
-    put_x(xf, w.x);
-    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "workgroup");
-    layer64<32>(w.x, P.w1t, P.b1, acc);
-    tanh_store(acc, w.ha, hidden, s0, n);
-    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "workgroup");
-    layer64<kH>(w.ha, P.w2t, P.b2, acc);
-    tanh_store(acc, w.hb, hidden ? hidden + n * kH : nullptr, s0, n);
-    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "workgroup");
-    layer64<kH>(w.hb, P.w3t, P.b3, acc);   // (the reads of ha above completed in order)
-    tanh_store(acc, w.ha, hidden ? hidden + 2 * n * kH : nullptr, s0, n);
-    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "workgroup");
     const int l = lane();
-    const float bias = P.b4[l & 15];
-    f32x4 o = f32x4{bias, bias, bias, bias};
+    const int64_t e = (s0 + (l & 15)) * kIn, end = n * kIn;
 #pragma unroll
-    for (int kt = 0; kt < 2; ++kt)
-        o = mfma(ld8(&w.ha[l & 15][kt * 32 + 8 * (l >> 4)]), ld8(&P.w4t[l & 15][kt * 32 + 8 * (l >> 4)]), o);
-    out[0] = o;
+    for (int c = 0; c < kIn; ++c) {
+        const int64_t i = e + c;
+        const float a = x[i < end ? i : end - 1];
+        v[c] = (l < 16 && i < end) ? a : 0.0f;
+    }
+}
+
+// compiler-only ordering of the wave's LDS accesses (no wait instruction)
+__device__ __forceinline__ void lds_order() { asm volatile("" ::: "memory"); }
+
+// tanh of a layer's accumulators into the wave's tile (row = sample, four
+// consecutive units per lane and N-tile), optionally also to global memory
+__device__ __forceinline__ void act_store(const f32x4 acc[4], bf16 (*a)[kK2], bf16* __restrict__ g, int64_t s0,
+                                          int64_t n)
+{
+    const int l = lane(), r = l & 15;
+#pragma unroll
+    for (int nt = 0; nt < 4; ++nt) {
+        const int u = nt * 16 + 4 * (l >> 4);
+        bf16x4 h;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) h[i] = bf16(tanh_bf(acc[nt][i]));
+        *reinterpret_cast<bf16x4*>(&a[r][u]) = h;
+        if (g != nullptr && s0 + r < n) *reinterpret_cast<bf16x4*>(&g[(s0 + r) * kH + u]) = h;
+    }
+}
+
+// one hidden layer (64 -> 64) from the wave's tile, transposed as in layer64
+__device__ __forceinline__ void hidden_layer(const bf16 (*a)[kK2], const bf16 (*wt)[kK2], const float* b, f32x4 acc[4])
+{
+    const int l = lane(), r = l & 15, c = 8 * (l >> 4);
+    const bf16x8 x0 = ld8(&a[r][c]), x1 = ld8(&a[r][32 + c]);
+#pragma unroll
+    for (int nt = 0; nt < 4; ++nt) {
+        f32x4 v = *reinterpret_cast<const f32x4*>(&b[nt * 16 + 4 * (l >> 4)]);
+        v = mfma(ld8(&wt[nt * 16 + r][c]), x0, v);
+        acc[nt] = mfma(ld8(&wt[nt * 16 + r][32 + c]), x1, v);
+    }
 }
 
 __global__ __launch_bounds__(kBlock) void k_mlp_pack(const float* __restrict__ m, Packed* __restrict__ p)
@@ -266,30 +303,54 @@ __global__ __launch_bounds__(kBlock) void k_mlp_pack(const float* __restrict__ m
 __global__ __launch_bounds__(kFwdBlock) void k_mlp_fwd(const Packed* __restrict__ gp, const float* __restrict__ x,
                                                        int64_t n, float* __restrict__ y, bf16* __restrict__ hidden)
 {
-    __shared__ PackedFwd P;
-    __shared__ FwdLds wl[kFwdBlock / 64];
-    stage_params(P, gp);
+    __shared__ FwdParams P;
+    __shared__ bf16 tile[kFwdBlock / 64][kTile][kK2];
+    stage_fwd(P, gp);
     __syncthreads();
-    FwdLds& w = wl[threadIdx.x >> 6];
-    const int l = lane();
-    for (int k = l; k < kTile * 32; k += 64) w.x[k >> 5][k & 31] = bf16(0.0f);
+    bf16 (*a)[kK2] = tile[threadIdx.x >> 6];
+    const int l = lane(), r = l & 15, c = 8 * (l >> 4);
     const int64_t tiles = (n + kTile - 1) / kTile;
     const int64_t t0 = int64_t(blockIdx.x) * (kFwdBlock / 64) + (threadIdx.x >> 6);
     const int64_t stride = int64_t(gridDim.x) * (kFwdBlock / 64);
-    XFetch xf = fetch_x(x, t0 * kTile, n);
+    bf16* const h2 = hidden ? hidden + n * kH : nullptr;
+    bf16* const h3 = hidden ? hidden + 2 * n * kH : nullptr;
+    float xv[kIn];
+    fetch_x(x, t0 * kTile, n, xv);
     for (int64_t t = t0; t < tiles; t += stride) {
         const int64_t s0 = t * kTile;
-        const XFetch cur = xf;
-        xf = fetch_x(x, (t + stride) * kTile, n);   // the next tile's inputs, in flight meanwhile
-        f32x4 o[1];
-        forward_tile_inf(P, w, cur, s0, n, hidden, o);
-        if ((l & 15) < kOut)
+        bf16x8 xb;
+#pragma unroll
+        for (int k = 0; k < kIn; ++k) xb[k] = bf16(xv[k]);
+#pragma unroll
+        for (int k = kIn; k < 8; ++k) xb[k] = bf16(0.0f);
+        fetch_x(x, s0 + stride * kTile, n, xv);   // the next tile's inputs, in flight meanwhile
+        f32x4 acc[4];
+#pragma unroll
+        for (int nt = 0; nt < 4; ++nt)
+            acc[nt] = mfma(ld8(&P.w1t[nt * 16 + r][c]), xb,
+                           *reinterpret_cast<const f32x4*>(&P.b1[nt * 16 + 4 * (l >> 4)]));
+        act_store(acc, a, hidden, s0, n);
+        lds_order();
+        hidden_layer(a, P.w2t, P.b2, acc);
+        lds_order();
+        act_store(acc, a, h2, s0, n);
+        lds_order();
+        hidden_layer(a, P.w3t, P.b3, acc);
+        lds_order();
+        act_store(acc, a, h3, s0, n);
+        lds_order();
+        // output layer, not transposed: lane l holds samples 4(l/16) .. + 3 of unit l % 16
+        const float bias = P.b4[r];
+        f32x4 o = f32x4{bias, bias, bias, bias};
+        o = mfma(ld8(&a[r][c]), ld8(&P.w4t[r][c]), o);
+        o = mfma(ld8(&a[r][32 + c]), ld8(&P.w4t[r][32 + c]), o);
+        if (r < kOut)
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
                 const int64_t s = s0 + 4 * (l >> 4) + i;
-                if (s < n) y[s * kOut + (l & 15)] = o[0][i];
+                if (s < n) y[s * kOut + r] = o[i];
             }
-        __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "workgroup");
+        lds_order();
     }
 }
 
