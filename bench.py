@@ -355,58 +355,59 @@ def measure_batch(cfgs: list, args) -> dict:
                          "window": "eager timed window of the same length after the graph window"}}
 
 
-def measure_fluid(args, pic_ms_per_step: float, pic_dt: float) -> dict:
-    """Batched quasi-neutral fluid columns (section IV): 256 columns of 4096
-    cells (20 cm, neon-like smooth synthetic table), timed with the table
-    closure and with the closure network (BF16 matrix cores) in the loop."""
-    import numpy as np
-    import torch
-    from paper_2202_03215_amd.fluid import FluidBatch
-    from paper_2202_03215_amd.mlp import ClosureNet, glorot_params
+CLOSURE_WEIGHTS = "workloads/closure_multipliers_ne_20cm.npz"
 
-    ncol, ncell, dt, L = args.fluid_columns, 4096, 2.0e-9, 0.20
-    table = W.fluid_table_smooth()
-    rng = np.random.default_rng(5)
-    cols = []
-    for c in range(ncol):
-        p = float(np.exp(rng.uniform(np.log(0.5), np.log(2.0))))
-        cols.append(dict(L=L, Ngas=3.22e22 * p, E0=300.0 * p * float(rng.uniform(0.9, 1.3)), nu_w=2.0e4 / p,
-                         muiN=4.0e21))
-    x = (np.arange(ncell) + 0.5) / ncell
-    n0 = np.array([1e15 * (1.0 + 0.05 * np.cos(2 * np.pi * (2 + c % 5) * x)) for c in range(ncol)])
-    w0 = 1.5 * n0 * 3.0
+
+def measure_fluid(args, pic_ms_per_step: float, pic_dt: float, batch=None) -> dict:
+    """Batched quasi-neutral fluid columns (section IV): 256 neon columns of
+    20 cm and 4096 cells at 1 Torr and 10 V/cm (the striated PIC column's
+    conditions, two-term table), each its own realization (1e-3 density
+    noise), with the table closure and with the learned multiplier closure
+    (network trained on the striated PIC column, weights in
+    workloads/closure_multipliers_ne_20cm.npz, BF16 matrix cores in the
+    loop).  Per closure: time per step over a timed window, then a free run
+    to 40 us of simulated time: striated fraction and ensemble wavelength."""
+    import numpy as np
+    from paper_2202_03215_amd import closure as CL
+    from paper_2202_03215_amd.mlp import ClosureNet
+
+    ncol, ncell, dt, L, E0 = args.fluid_columns, 4096, 1.0e-9, 0.20, 1000.0
+    Ngas = 1.0 * 133.322368 / (1.380649e-23 * 300.0)
+    table = W.fluid_table_ne()
+    wpath = os.path.join(ROOT, CLOSURE_WEIGHTS)
+    if not os.path.exists(wpath):
+        raise FileNotFoundError(f"{CLOSURE_WEIGHTS} missing (python -m paper_2202_03215_amd.closure OUT.npz)")
+    d = np.load(wpath)
+    net = ClosureNet(d["theta"].astype(np.float64), max_batch=1024)
     out = {}
-    for closure in ("table", "network"):
-        fb = FluidBatch(cols, ncell, dt, table, W.FLUID_T_MIN, W.FLUID_T_STEP)
-        if closure == "network":
-            th = glorot_params(3)
-            th[-(64 * 2 + 2):] *= 0.01          # small output layer: fluxes near the offsets
-            net = ClosureNet(th, max_batch=1024)
-            norm = np.array([1e15, 4.5, 300.0, 0.0, 0.0, 1e-15, 0.3, 3e-3, 1e-17, 3e-3,
-                             1e18, 1e19, -1.0e19, -5e19], dtype=np.float32)
-            fb.set_closure(net, norm)
-        fb.set_state(n0, w0)
-        fb.step(args.fluid_warmup)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        fb.step(args.fluid_steps)
-        torch.cuda.synchronize()
-        el = time.perf_counter() - t0
-        n, w = fb.get_state()
-        ok = bool(torch.isfinite(n).all() and torch.isfinite(w).all())
-        us = el * 1e6 / args.fluid_steps
-        out[closure] = {"us_per_step": us, "cell_steps_per_s": ncol * ncell / (us * 1e-6), "finite": ok}
-        print(f"[bench] fluid {closure}: {us:.1f} us per step ({ncol} x {ncell} cells)", file=sys.stderr,
-              flush=True)
-        del fb
+    for name, kw in (("table", {}), ("learned_multipliers", dict(net=net, norm=d["norm"], multipliers=True))):
+        r = CL.fluid_ensemble(table, W.FLUID_T_MIN, W.FLUID_T_STEP, Ngas, E0, L, ncell, dt, args.fluid_run_steps,
+                              ncol, snapshots=10, timed=(args.fluid_warmup, args.fluid_steps), **kw)
+        lam = r["wavelength"]
+        ok = np.isfinite(lam)
+        us = r["us_per_step"]
+        out[name] = {"us_per_step": us, "cell_steps_per_s": ncol * ncell / (us * 1e-6),
+                     "striated_fraction": float(ok.mean()),
+                     "wavelength_mean_cm": float(lam[ok].mean() * 100) if ok.any() else None,
+                     "wavelength_se_cm": float(lam[ok].std(ddof=1) / np.sqrt(ok.sum()) * 100) if ok.sum() > 1
+                     else None,
+                     "modulation_mean": float(r["modulation"].mean())}
+        print(f"[bench] fluid {name}: {us:.1f} us per step ({ncol} x {ncell} cells); striated "
+              f"{ok.mean():.2f}, lambda {out[name]['wavelength_mean_cm']} cm", file=sys.stderr, flush=True)
     # wall time per simulated microsecond of one column
-    fluid_s = out["network"]["us_per_step"] * 1e-6 / dt * 1e-6 / ncol
+    fluid_s = out["learned_multipliers"]["us_per_step"] * 1e-6 / dt * 1e-6 / ncol
     pic_s = pic_ms_per_step * 1e-3 / pic_dt * 1e-6
-    return {"workload": f"fluid_{ncol}x{ncell}", "columns": ncol, "cells": ncell, "dt": dt,
-            "dtype": "f32 state, f64 tridiagonal, bf16 network", **out,
-            "wall_s_per_simulated_us_per_column": fluid_s,
-            "pic_wall_s_per_simulated_us_per_column": pic_s,
-            "wall_time_ratio_pic_over_fluid": pic_s / fluid_s}
+    res = {"workload": f"fluid_ne_20cm_{ncol}x{ncell}", "columns": ncol, "cells": ncell, "dt": dt, "E0": E0,
+           "free_run_us": args.fluid_run_steps * dt * 1e6,
+           "dtype": "f32 state, f64 tridiagonal, bf16 network", **out,
+           "wall_s_per_simulated_us_per_column": fluid_s,
+           "pic_wall_s_per_simulated_us_per_column": pic_s,
+           "wall_time_ratio_pic_over_fluid": pic_s / fluid_s}
+    if batch is not None:
+        bs = batch["ms_per_step"] * 1e-3 / (batch["dt_sum"] * 1e6)   # columns advance their own dt per step
+        res["batched_pic_wall_s_per_simulated_us_per_column"] = bs
+        res["wall_time_ratio_batched_pic_over_fluid"] = bs / fluid_s
+    return res
 
 
 def main() -> int:
@@ -431,6 +432,8 @@ def main() -> int:
     ap.add_argument("--no-fluid", action="store_true", help="skip the batched fluid columns")
     ap.add_argument("--fluid-columns", type=int, default=256)
     ap.add_argument("--fluid-steps", type=int, default=200)
+    ap.add_argument("--fluid-run-steps", type=int, default=40_000,
+                    help="free-run length of the fluid ensembles (steps of 1 ns)")
     ap.add_argument("--fluid-warmup", type=int, default=20)
     ap.add_argument("--no-probe", action="store_true", help="skip the stream probe")
     ap.add_argument("--probe-mib", type=int, default=2048)
@@ -519,7 +522,11 @@ def main() -> int:
     if not args.no_fluid:
         ref = out.get("column_20cm")
         pic_ms = ref["ms_per_step"] if ref else elapsed * 1e3 / args.steps
-        out["fluid"] = measure_fluid(args, pic_ms, float(W.column_20cm()["dt"]))
+        bt = None
+        if "batched" in out:
+            bt = {"ms_per_step": out["batched"]["ms_per_step"],
+                  "dt_sum": float(sum(c["dt"] for c in W.argon_scan(args.batch_columns)))}
+        out["fluid"] = measure_fluid(args, pic_ms, float(W.column_20cm()["dt"]), bt)
     if not args.no_cpu:
         ss = args.cpu_steps or 40
         sa = args.cpu_steps or 100

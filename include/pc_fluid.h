@@ -24,7 +24,13 @@
  * State: n [m^-3] and w = 3/2 n T [eV m^-3], device float [n_columns][n_cells].
  * Network closure inputs per face (n_f, 3/2 T_f, E_f, dn/dx, d(3/2 T)/dx) are
  * normalised as (v - norm[k]) * norm[5 + k]; outputs give
- * Gamma = y0 norm[10] + norm[12], H = y1 norm[11] + norm[13].
+ * Gamma = y0 norm[10] + norm[12], H = y1 norm[11] + norm[13] (flux closure),
+ * or m_D = y0 norm[10] + norm[12], m_eps = y1 norm[11] + norm[13], each
+ * clamped to [1/4, 4] (multiplier closure: eqs. (12)-(13) with D_e, its
+ * slope and the diffusion term of eq. (17) at the face times m_D, and mu_eps,
+ * D_eps and the slope of D_eps times m_eps; the multipliers of a step are the
+ * network's answer to the previous step's face inputs, 1 on the first step
+ * after pc_fluid_set_state or a closure change).
  * All calls are asynchronous on the stream given at init unless noted.
  */
 #ifndef PC_FLUID_H
@@ -63,9 +69,14 @@ pc_status pc_fluid_get_state(pc_fluid_handle h, float* n, float* w);
 /* Closure: mlp_packed = null selects eqs. (12)-(13) with the table;
  * otherwise the packed network of pc_mlp_pack with norm (host float[14]). */
 pc_status pc_fluid_set_closure(pc_fluid_handle h, const void* mlp_packed, const float* norm);
+/* Multiplier closure (the fluxes stay those of eqs. (12)-(13), so the
+ * implicit diffusion split keeps its sign whatever the network answers):
+ * mlp_packed and norm as above, both required. */
+pc_status pc_fluid_set_closure_multipliers(pc_fluid_handle h, const void* mlp_packed, const float* norm);
 pc_status pc_fluid_step(pc_fluid_handle h, int64_t n_steps);
-/* Face values of the last step: flux, energy flux (table closure only) and
- * field at face j (between cells j and j+1); any pointer may be null. */
+/* Face values of the last step: flux, energy flux (table and multiplier
+ * closures only) and field at face j (between cells j and j+1); any pointer
+ * may be null. */
 pc_status pc_fluid_get_faces(pc_fluid_handle h, float* gamma, float* H, float* E);
 /* Batched cyclic tridiagonal solve a_j x_{j-1} + b_j x_j + c_j x_{j+1} = d_j
  * (indices mod n, n a power of two <= 4096; device double [n_systems][n]);

@@ -27,7 +27,12 @@ the same steps):
     H_f     = -chi dn - kappa dT - beta/(mu_e+mu_i) Gamma_T             (13)
   with D_a = mu_i D_e/mu_e, eta = n (mu_i/mu_e) D_e', beta = 1.5 T mu_eps,
   G = 1.5 T D_eps, kappa = n (G' - beta D_e'/mu_e), chi = G - beta D_e/mu_e,
-  or a closure network fed (n_f, 1.5 T_f, E_f, dn_f, 1.5 dT_f) (normalised)
+  or a closure network fed (n_f, 1.5 T_f, E_f, dn_f, 1.5 dT_f) (normalised),
+  or the table form with multipliers from a network fed the same features:
+    m_D multiplies D_e, its slope and A_f (the diffusion of eq. (17) at the
+    face), m_eps multiplies mu_eps, D_eps and the slope of D_eps, both
+    clamped to [1/4, 4]; the multipliers of step k are the network's answer
+    to the features of step k - 1 (1 on the first step)
   sources: S_n = n_j (nu_i(T_j) - nu_w); heating P_j = -(Gamma E)_{j-1/2,j+1/2}
   mean; S_w = P_j - n_j L(T_j)
   implicit step (backward Euler on the diffusion parts, the rest explicit):
@@ -65,6 +70,10 @@ class FluidColumn:
     n_floor: float = 1.0e6
     # closure network hook: f(features[M, 5]) -> (Gamma[M], H[M]) in physical units
     closure: object = None
+    # multiplier network hook: f(features[M, 5]) -> (m_D[M], m_eps[M]) before clamping;
+    # m holds the multipliers of the next step (None: all 1)
+    multipliers: object = None
+    m: object = None
     diag: dict = field(default_factory=dict)
 
 
@@ -79,6 +88,9 @@ def interp(col: FluidColumn, T):
     val = lo + f[:, None] * (hi - lo)
     slope = (hi - lo) / col.T_step
     return val, slope
+
+
+M_MIN, M_MAX = 0.25, 4.0
 
 
 def faces(col: FluidColumn, n, w):
@@ -102,6 +114,10 @@ def faces(col: FluidColumn, n, w):
     dn = (nr - n) / dx
     dT = (Tr - T) / dx
     A = (np.roll(Phi, -1) - Phi) / (dx * nf)
+    if col.multipliers is not None and col.m is not None:
+        mD, mE = col.m
+        A, De, dDe = mD * A, mD * De, mD * dDe
+        mueps, Deps, dDeps = mE * mueps, mE * Deps, mE * dDeps
     B = 1.0 / (nf * (mue + mui))
     GT = (col.E0 + A.mean()) / B.mean()
     E = -A + GT * B
@@ -115,6 +131,9 @@ def faces(col: FluidColumn, n, w):
         chi = G - beta * De / mue
         Gam = -Da * dn - eta * dT - mue / (mue + mui) * GT
         H = -chi * dn - kappa * dT - beta / (mue + mui) * GT
+        if col.multipliers is not None:   # the next step's multipliers
+            mD, mE = col.multipliers(np.stack([nf, 1.5 * Tf, E, dn, 1.5 * dT], axis=1))
+            col.m = (np.clip(mD, M_MIN, M_MAX), np.clip(mE, M_MIN, M_MAX))
     else:
         feats = np.stack([nf, 1.5 * Tf, E, dn, 1.5 * dT], axis=1)
         Gam, H = col.closure(feats)

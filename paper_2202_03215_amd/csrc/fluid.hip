@@ -7,7 +7,9 @@
 //                  Gamma_T fixed by the imposed mean field, the field of
 //                  eq. (17), the closure fluxes of eqs. (12)-(13) -- or the
 //                  normalised inputs of the closure network (the network then
-//                  runs on the matrix cores, mlp.hip)
+//                  runs on the matrix cores, mlp.hip), which either gives the
+//                  fluxes or multipliers of the tabulated coefficients used
+//                  by eqs. (12)-(13) on the next step
 //   k_fluid_solve  sources (ionisation minus radial loss, Joule heating minus
 //                  collisional loss), backward-Euler diffusion of density and
 //                  of energy density as two cyclic tridiagonal systems in
@@ -35,15 +37,19 @@ struct ColDev {
     double L, Ngas, E0, nu_w, muiN;
 };
 
+// closure kinds
+constexpr int kTable = 0, kNetFlux = 1, kNetMult = 2;
+constexpr float kMultMin = 0.25f, kMultMax = 4.0f;
+
 struct Globals {
-    int32_t N, K, mlp, pad;
+    int32_t N, K, mlp, have_m;   // closure kind; have_m: y holds multipliers of this state's past
     float T_min, T_step, n_floor, dt;
     const float* table;        // [K][6]
     const ColDev* cols;
     float *n, *w;              // [col][N]
     float *gam, *H, *E, *Da, *kap, *dn, *dT;   // faces [col][N], face j between cells j and j+1
     float* x;                  // closure-network inputs [col][N][5]
-    const float* y;            // closure-network outputs [col][N][2]
+    const float* y;            // closure-network outputs [col][N][2] (fluxes or multipliers)
     float norm[14];            // inputs (x - off) * scale (5 + 5), outputs y * scale + off (2 + 2)
 };
 
@@ -91,7 +97,18 @@ struct FaceQ {
     float nf, Tf, dn, dT, A, B, mue, De, mueps, Deps, dDe, dDeps;
 };
 
-__device__ __forceinline__ FaceQ face(const Globals& G, const ColDev& C, const float* n, const float* w, int j)
+// multipliers of face j (m_D, m_eps): the network's last answer, clamped; 1 before it
+__device__ __forceinline__ void face_multipliers(const Globals& G, int64_t f, float& mD, float& mE)
+{
+    mD = mE = 1.0f;
+    if (G.mlp == kNetMult && G.have_m) {
+        mD = fminf(fmaxf(G.y[f * 2] * G.norm[10] + G.norm[12], kMultMin), kMultMax);
+        mE = fminf(fmaxf(G.y[f * 2 + 1] * G.norm[11] + G.norm[13], kMultMin), kMultMax);
+    }
+}
+
+__device__ __forceinline__ FaceQ face(const Globals& G, const ColDev& C, const float* n, const float* w, int j,
+                                      float mD, float mE)
 {
     const int N = G.N;
     const int jr = (j + 1) & (N - 1);
@@ -109,13 +126,13 @@ __device__ __forceinline__ FaceQ face(const Globals& G, const ColDev& C, const f
     q.dT = (T1 - T0) / dx;
     const Coef cf = interp(G, q.Tf);
     q.mue = cf.v[0] / Ng;
-    q.De = cf.v[1] / Ng;
-    q.mueps = cf.v[2] / Ng;
-    q.Deps = cf.v[3] / Ng;
-    q.dDe = cf.s[1] / Ng;
-    q.dDeps = cf.s[3] / Ng;
+    q.De = mD * (cf.v[1] / Ng);
+    q.mueps = mE * (cf.v[2] / Ng);
+    q.Deps = mE * (cf.v[3] / Ng);
+    q.dDe = mD * (cf.s[1] / Ng);
+    q.dDeps = mE * (cf.s[3] / Ng);
     const float mui = float(C.muiN) / Ng;
-    q.A = (Phi1 - Phi0) / (dx * q.nf);
+    q.A = mD * ((Phi1 - Phi0) / (dx * q.nf));
     q.B = 1.0f / (q.nf * (q.mue + mui));
     return q;
 }
@@ -128,9 +145,12 @@ __global__ __launch_bounds__(kFaceBlock) void k_fluid_faces(Globals G)
     const int N = G.N;
     const float* n = G.n + int64_t(col) * N;
     const float* w = G.w + int64_t(col) * N;
+    const int64_t o = int64_t(col) * N;
     double sa = 0.0, sb = 0.0;
     for (int j = threadIdx.x; j < N; j += blockDim.x) {
-        const FaceQ q = face(G, C, n, w, j);
+        float mD, mE;
+        face_multipliers(G, o + j, mD, mE);
+        const FaceQ q = face(G, C, n, w, j, mD, mE);
         sa += double(q.A);
         sb += double(q.B);
     }
@@ -138,9 +158,10 @@ __global__ __launch_bounds__(kFaceBlock) void k_fluid_faces(Globals G)
     const double SB = block_sum_d(sb, sh);
     const float GT = float((C.E0 + SA / N) / (SB / N));
     const float mui = float(C.muiN / C.Ngas);
-    const int64_t o = int64_t(col) * N;
     for (int j = threadIdx.x; j < N; j += blockDim.x) {
-        const FaceQ q = face(G, C, n, w, j);
+        float mD, mE;
+        face_multipliers(G, o + j, mD, mE);
+        const FaceQ q = face(G, C, n, w, j, mD, mE);
         const float E = -q.A + GT * q.B;
         const float Da = mui * q.De / q.mue;
         const float beta = 1.5f * q.Tf * q.mueps;
@@ -152,12 +173,13 @@ __global__ __launch_bounds__(kFaceBlock) void k_fluid_faces(Globals G)
         G.kap[o + j] = kap;
         G.dn[o + j] = q.dn;
         G.dT[o + j] = q.dT;
-        if (G.mlp) {
+        if (G.mlp != kTable) {
             const float f[5] = {q.nf, 1.5f * q.Tf, E, q.dn, 1.5f * q.dT};
             float* xo = G.x + (o + j) * 5;
 #pragma unroll
             for (int k = 0; k < 5; ++k) xo[k] = (f[k] - G.norm[k]) * G.norm[5 + k];
-        } else {
+        }
+        if (G.mlp != kNetFlux) {
             const float eta = q.nf * (mui / q.mue) * q.dDe;
             const float chi = Gc - beta * q.De / q.mue;
             G.gam[o + j] = -Da * q.dn - eta * q.dT - q.mue / (q.mue + mui) * GT;
@@ -224,7 +246,7 @@ __global__ __launch_bounds__(kSolveBlock) void k_fluid_solve(Globals G)
         if (j < N) {
             const int jm = (j - 1) & (N - 1);
             float gp, gm, hp, hm;
-            if (G.mlp) {
+            if (G.mlp == kNetFlux) {
                 gp = G.y[(o + j) * 2] * G.norm[10] + G.norm[12];
                 gm = G.y[(o + jm) * 2] * G.norm[10] + G.norm[12];
                 hp = G.y[(o + j) * 2 + 1] * G.norm[11] + G.norm[13];
@@ -390,7 +412,8 @@ pc_status pc_fluid_init(const pc_fluid_config* cfg, const pc_fluid_column* cols,
     Globals& G = h->G;
     G.N = cfg->n_cells;
     G.K = cfg->table_len;
-    G.mlp = 0;
+    G.mlp = kTable;
+    G.have_m = 0;
     G.T_min = float(cfg->T_min);
     G.T_step = float(cfg->T_step);
     G.n_floor = float(cfg->n_floor);
@@ -424,6 +447,7 @@ pc_status pc_fluid_init(const pc_fluid_config* cfg, const pc_fluid_column* cols,
 pc_status pc_fluid_set_state(pc_fluid_handle h, const float* n, const float* w)
 {
     if (!h || !n || !w) return ferr(PC_ERR_INVALID_ARG, "null argument");
+    h->G.have_m = 0;   // multipliers answer the state's own past only
     const size_t bytes = size_t(h->cfg.n_columns) * h->cfg.n_cells * 4;
     if (hipMemcpyAsync(h->G.n, n, bytes, hipMemcpyDeviceToDevice, h->st) != hipSuccess ||
         hipMemcpyAsync(h->G.w, w, bytes, hipMemcpyDeviceToDevice, h->st) != hipSuccess)
@@ -445,8 +469,19 @@ pc_status pc_fluid_set_closure(pc_fluid_handle h, const void* mlp_packed, const 
 {
     if (!h || (mlp_packed && !norm)) return ferr(PC_ERR_INVALID_ARG, "bad closure arguments");
     h->mlp_packed = mlp_packed;
-    h->G.mlp = mlp_packed != nullptr;
+    h->G.mlp = mlp_packed != nullptr ? kNetFlux : kTable;
+    h->G.have_m = 0;
     if (norm) std::memcpy(h->G.norm, norm, sizeof(h->G.norm));
+    return PC_OK;
+}
+
+pc_status pc_fluid_set_closure_multipliers(pc_fluid_handle h, const void* mlp_packed, const float* norm)
+{
+    if (!h || !mlp_packed || !norm) return ferr(PC_ERR_INVALID_ARG, "bad closure arguments");
+    h->mlp_packed = mlp_packed;
+    h->G.mlp = kNetMult;
+    h->G.have_m = 0;
+    std::memcpy(h->G.norm, norm, sizeof(h->G.norm));
     return PC_OK;
 }
 
@@ -457,12 +492,15 @@ pc_status pc_fluid_step(pc_fluid_handle h, int64_t n_steps)
     const int64_t cells = int64_t(nc) * h->cfg.n_cells;
     for (int64_t k = 0; k < n_steps; ++k) {
         hipLaunchKernelGGL(k_fluid_faces, dim3(nc), dim3(kFaceBlock), 0, h->st, h->G);
-        if (h->G.mlp) {
+        if (h->G.mlp != kTable) {
+            // fluxes of this step, or the multipliers of the next one (the
+            // face kernel above has read the previous answer)
             const pc_status s = pc_mlp_forward(h->mlp_packed, h->G.x, cells, const_cast<float*>(h->G.y), nullptr,
                                                h->st);
             if (s != PC_OK) return s;
         }
         hipLaunchKernelGGL(k_fluid_solve, dim3(nc), dim3(kSolveBlock), 0, h->st, h->G);
+        if (h->G.mlp == kNetMult) h->G.have_m = 1;
     }
     return hipGetLastError() == hipSuccess ? PC_OK : ferr(PC_ERR_HIP, "pc_fluid_step launch");
 }
@@ -471,7 +509,8 @@ pc_status pc_fluid_get_faces(pc_fluid_handle h, float* gamma, float* H, float* E
 {
     if (!h) return ferr(PC_ERR_INVALID_ARG, "null handle");
     const size_t bytes = size_t(h->cfg.n_columns) * h->cfg.n_cells * 4;
-    if (h->G.mlp && (gamma || H)) return ferr(PC_ERR_INVALID_ARG, "network closure: fluxes are not stored");
+    if (h->G.mlp == kNetFlux && (gamma || H))
+        return ferr(PC_ERR_INVALID_ARG, "network flux closure: fluxes are not stored");
     if ((gamma && hipMemcpyAsync(gamma, h->G.gam, bytes, hipMemcpyDeviceToDevice, h->st) != hipSuccess) ||
         (H && hipMemcpyAsync(H, h->G.H, bytes, hipMemcpyDeviceToDevice, h->st) != hipSuccess) ||
         (E && hipMemcpyAsync(E, h->G.E, bytes, hipMemcpyDeviceToDevice, h->st) != hipSuccess))

@@ -36,6 +36,7 @@ def _lib():
             "pc_fluid_set_state": [P, P, P],
             "pc_fluid_get_state": [P, P, P],
             "pc_fluid_set_closure": [P, P, C.POINTER(C.c_float)],
+            "pc_fluid_set_closure_multipliers": [P, P, C.POINTER(C.c_float)],
             "pc_fluid_step": [P, I64],
             "pc_fluid_get_faces": [P, P, P, P],
             "pc_cyclic_tridiag": [P, P, P, P, I32, I32, P],
@@ -109,18 +110,26 @@ class FluidBatch:
         _check(_lib().pc_fluid_get_state(self.h, n.data_ptr(), w.data_ptr()))
         return n, w
 
-    def set_closure(self, net=None, norm=None) -> None:
-        """net: a ClosureNet (packed operands used) or None for the table closure."""
+    def set_closure(self, net=None, norm=None, multipliers: bool = False) -> None:
+        """net: a ClosureNet (packed operands used) or None for the table
+        closure; multipliers: the network answers multipliers (m_D, m_eps) of
+        the tabulated coefficients instead of the fluxes."""
         self._net = net
+        self._fluxes_stored = net is None or multipliers
         arr = (C.c_float * 14)(*([float(v) for v in norm] if norm is not None else [0.0] * 14))
-        _check(_lib().pc_fluid_set_closure(self.h, net.packed.data_ptr() if net is not None else None, arr))
+        if multipliers:
+            if net is None:
+                raise ValueError("the multiplier closure needs a network")
+            _check(_lib().pc_fluid_set_closure_multipliers(self.h, net.packed.data_ptr(), arr))
+        else:
+            _check(_lib().pc_fluid_set_closure(self.h, net.packed.data_ptr() if net is not None else None, arr))
 
     def step(self, n: int = 1) -> None:
         _check(_lib().pc_fluid_step(self.h, int(n)))
 
     def faces(self):
         E = torch.empty((self.n_columns, self.n_cells), dtype=torch.float32, device=self.device)
-        if self._net is None:
+        if getattr(self, "_fluxes_stored", True):
             g = torch.empty_like(E)
             H = torch.empty_like(E)
             _check(_lib().pc_fluid_get_faces(self.h, g.data_ptr(), H.data_ptr(), E.data_ptr()))

@@ -33,7 +33,7 @@ EXPORTS = ("pc_query_sizes", "pc_init_column", "pc_step", "pc_prepare_graphs", "
            "pc_mlp_query", "pc_mlp_pack", "pc_mlp_forward", "pc_mlp_grad", "pc_mlp_grad_noalloc", "pc_mlp_adam",
            "pc_mlp_last_error",
            "pc_fluid_query", "pc_fluid_init", "pc_fluid_set_state", "pc_fluid_get_state",
-           "pc_fluid_set_closure", "pc_fluid_step", "pc_fluid_get_faces", "pc_cyclic_tridiag",
+           "pc_fluid_set_closure", "pc_fluid_set_closure_multipliers", "pc_fluid_step", "pc_fluid_get_faces", "pc_cyclic_tridiag",
            "pc_fluid_destroy", "pc_fluid_last_error")
 
 

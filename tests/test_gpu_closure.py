@@ -77,3 +77,53 @@ def test_sample_pipeline_against_table_closure_in_a_uniform_column(torch_cuda):
         r = Y[:, k].mean() / pt[:, k].mean()
         print(f"uniform column, output {k}: PIC / table = {r:.3f}")
         assert abs(r - 1.0) < 0.10, (k, r)
+
+
+def test_multiplier_closure_on_striated_pic_columns(torch_cuda):
+    """The learned closure in multiplier form (network answers m_D for the
+    electron diffusion and m_eps for the energy transport of the two-term
+    table) trained on the striated 20 cm neon column (1 Torr, 10 V/cm,
+    saturated ionization wave), evaluated on a held-out realization.
+
+    What it gains: the table's local drift-diffusion fluxes at the PIC
+    column's own field and gradients miss the PIC fluxes by far (normalised
+    MSE in the hundreds for the electron flux); the learned multipliers
+    bring it down by more than 10x, and the energy flux error below 0.8x.
+    What it finds (recorded reading, not a goal): the PIC's effective
+    electron diffusion is a fraction of the local two-term value (global
+    least-squares m_D below 0.6), and a fluid column carrying these
+    multipliers does not striate at this field (the fluid model's own
+    instability needs the local-field diffusion), while the table closure
+    does."""
+    import workloads as W
+    from paper_2202_03215_amd import closure as CL
+    from tests.gpu_helpers import striation_config
+    cfgs = [striation_config("20cm", s) for s in (1, 2)]
+    X, Y, col = CL.striated_samples(cfgs, warm=100_000, steps=50_000, every=5, window=500, group=4)
+    Ngas = 1.0 * 133.322368 / (1.380649e-23 * 300.0)
+    T = W.FLUID_T_MIN + W.FLUID_T_STEP * np.arange(W.FLUID_T_LEN)
+    tab = W.fluid_table_ne()
+    tr, te = col == 0, col == 1
+    M = CL.multiplier_targets(X[tr], Y[tr], T, tab, Ngas, k=64)
+    net, norm, losses = CL.train(X[tr], M, steps=2000, lr=2e-3, batch=4096, seed=0)
+    assert np.all(np.isfinite(losses)) and losses[-100:].mean() < losses[:10].mean()
+    drift, diff, Ht = CL.table_terms(X[te], T, tab, Ngas)
+    m = np.clip(CL.predict(net, X[te], norm), 0.25, 4.0)
+    pt = CL.table_fluxes(X[te], T, tab, Ngas)
+    pm = np.stack([drift + m[:, 0] * diff, m[:, 1] * Ht], axis=1)
+    e_table = [np.mean((pt[:, k] - Y[te, k]) ** 2) / np.var(Y[te, k]) for k in range(2)]
+    e_net = [np.mean((pm[:, k] - Y[te, k]) ** 2) / np.var(Y[te, k]) for k in range(2)]
+    dr, df, _ = CL.table_terms(X[tr], T, tab, Ngas)
+    mD = float((df * (Y[tr, 0] - dr)).sum() / (df ** 2).sum())
+    print(f"held-out normalised MSE: electron flux table {e_table[0]:.1f} / learned {e_net[0]:.2f}, energy flux "
+          f"table {e_table[1]:.3f} / learned {e_net[1]:.3f}; global m_D {mD:.3f}")
+    assert e_net[0] < 0.1 * e_table[0] and e_net[1] < 0.8 * e_table[1]
+    assert mD < 0.6
+    runs = {}
+    for name, kw in (("table", {}), ("learned", dict(net=net, norm=norm, multipliers=True))):
+        r = CL.fluid_ensemble(tab, W.FLUID_T_MIN, W.FLUID_T_STEP, Ngas, 1000.0, 0.2, 1024, 1e-9, 20_000, 16, **kw)
+        runs[name] = r
+        print(name, "striated fraction", np.isfinite(r["wavelength"]).mean(), "modulation",
+              np.round(r["modulation"], 2).tolist())
+    assert np.isfinite(runs["table"]["wavelength"]).mean() >= 0.5
+    assert np.isfinite(runs["learned"]["wavelength"]).mean() == 0.0    # no column reaches modulation 0.2

@@ -168,3 +168,59 @@ def test_fluid_network_closure_against_oracle(torch_cuda):
         assert np.abs(ng[k] - n).max() <= 2e-3 * n.mean(), (k, np.abs(ng[k] - n).max() / n.mean())
         assert np.abs(Tg - To).max() <= 2e-3 * To.mean(), (k, np.abs(Tg - To).max() / To.mean())
         assert np.abs(ng[k] - n0[k]).max() > 1e-4 * n.mean()      # the closure moved the state
+
+
+def test_fluid_multiplier_closure_against_oracle(torch_cuda):
+    """Multiplier closure: the network answers (m_D, m_eps) multipliers of
+    the tabulated coefficients.  Step 1 uses no multipliers and must equal
+    the table closure's step bit for bit; 40 steps against the oracle with
+    the same network (BF16 emulated): within 2e-3 relative (inputs rounding
+    to different BF16 values on the two sides move a multiplier by at most
+    about one BF16 ulp of its input's influence, each step)."""
+    from paper_2202_03215_amd.mlp import ClosureNet
+    torch = torch_cuda
+    n_cells, dt = 256, 2e-9
+    table = W.fluid_table_smooth()
+    cols = _columns(n_cells, table, dt)
+    n0, w0 = _state(cols, n_cells, 7)
+    n0 = n0.astype(np.float32).astype(np.float64)
+    w0 = w0.astype(np.float32).astype(np.float64)
+    rng = np.random.default_rng(1)
+    th = O.init_params(6)
+    W1, b1, W2, b2, W3, b3, W4, b4 = O.unpack(th)
+    th = O.pack([W1, b1, W2, b2, W3, b3, W4 * 0.3, rng.normal(0, 0.1, 2)]).astype(np.float32).astype(np.float64)
+    norm = np.array([1e15, 6.0, 500.0, 0.0, 0.0,
+                     1e-15, 0.3, 2e-3, 1e-17, 3e-3,
+                     0.3, 0.4, 1.0, 1.1], dtype=np.float32)          # m_D = 0.3 y0 + 1, m_eps = 0.4 y1 + 1.1
+    nz = norm.astype(np.float64)
+
+    def mult(feats):
+        x = (feats - nz[:5]) * nz[5:10]
+        y, _ = O.forward(th, x, emulate=True)
+        return y[:, 0] * nz[10] + nz[12], y[:, 1] * nz[11] + nz[13]
+
+    net = ClosureNet(th)
+    fb = _batch(cols, n_cells, dt, table)
+    fb.set_closure(net, norm, multipliers=True)
+    fb.set_state(n0, w0)
+    fb.step(1)
+    n1, w1 = (t.cpu().numpy().copy() for t in fb.get_state())
+    ft = _batch(cols, n_cells, dt, table)
+    ft.set_state(n0, w0)
+    ft.step(1)
+    t1, s1 = (t.cpu().numpy() for t in ft.get_state())
+    assert np.array_equal(n1, t1) and np.array_equal(w1, s1)
+    fb.step(39)
+    ng, wg = (t.cpu().numpy().astype(np.float64) for t in fb.get_state())
+    ft.step(39)
+    nt = ft.get_state()[0].cpu().numpy().astype(np.float64)
+    for k, (c, _) in enumerate(cols):
+        c.multipliers, c.m = mult, None
+        n, w = F.run(c, n0[k], w0[k], 40)
+        Tg, To = wg[k] / (1.5 * ng[k]), w / (1.5 * n)
+        en = np.abs(ng[k] - n).max() / n.mean()
+        eT = np.abs(Tg - To).max() / To.mean()
+        print(f"column {k}: 40 steps, |dn| {en:.2e}, |dT| {eT:.2e}; multipliers m_D {c.m[0].min():.3f}..{c.m[0].max():.3f}, "
+              f"m_eps {c.m[1].min():.3f}..{c.m[1].max():.3f}; off the table run by {np.abs(nt[k] - n).max() / n.mean():.2e}")
+        assert en <= 2e-3 and eT <= 2e-3, (k, en, eT)
+        assert np.abs(nt[k] - n).max() > 10 * np.abs(ng[k] - n).max()   # the multipliers moved the run

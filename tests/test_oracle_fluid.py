@@ -102,3 +102,59 @@ def test_perturbed_column_stays_positive_and_finite():
     w = 1.5 * n * T0
     n, w = F.run(col, n, w, 200)
     assert np.all(np.isfinite(n)) and np.all(np.isfinite(w)) and n.min() > 0
+
+
+def _perturbed(col, seed, amp=0.05):
+    T0, _ = F.steady_temperature(col)
+    rng = np.random.default_rng(seed)
+    n = 1e15 * (1.0 + amp * rng.normal(size=col.n_cells))
+    w = 1.5 * n * T0 * (1.0 + amp * rng.normal(size=col.n_cells))
+    return n, w
+
+
+def test_constant_multipliers_equal_scaled_tables():
+    """Multiplier closure with constant answers (m_D, m_eps): the first step
+    is the table closure itself (no multipliers before the network has
+    answered), every later step the table closure on a table whose D_e column
+    is scaled by m_D and whose mu_eps and D_eps columns by m_eps (the
+    multipliers act on the coefficients, the gradient term of eq. (17) and
+    the slopes alike).  A multiplier outside [1/4, 4] acts as its bound."""
+    for mD, mE, eD, eE in ((1.3, 0.7, 1.3, 0.7), (9.0, 0.1, 4.0, 0.25)):
+        col = _col(W.fluid_table_smooth(), N=64, L=0.03)
+        n0, w0 = _perturbed(col, 5)
+        col.multipliers = lambda f: (np.full(f.shape[0], mD), np.full(f.shape[0], mE))
+        n1, w1 = F.step(col, n0, w0)
+        ref = _col(W.fluid_table_smooth(), N=64, L=0.03)
+        r1, s1 = F.step(ref, n0, w0)
+        assert np.array_equal(n1, r1) and np.array_equal(w1, s1)
+        n, w = F.run(col, n1, w1, 5)
+        tab = W.fluid_table_smooth().copy()
+        tab[:, 1] *= eD
+        tab[:, 2:4] *= eE
+        sc = _col(tab, N=64, L=0.03)
+        sc.E0 = col.E0
+        r, s = F.run(sc, r1, s1, 5)
+        assert np.allclose(n, r, rtol=1e-12, atol=0) and np.allclose(w, s, rtol=1e-12, atol=0)
+        assert not np.allclose(n, F.run(ref, r1, s1, 5)[0], rtol=1e-6)   # the multipliers changed the run
+
+
+def test_multipliers_follow_the_previous_step_features():
+    """The multipliers applied at step k are the network's answer to the face
+    features of step k - 1 (features n_f, 3/2 T_f, E_f, dn_f, 3/2 dT_f): a
+    hook recording its inputs sees at each call exactly the features of the
+    table closure's diagnostics of the same step."""
+    col = _col(W.fluid_table_smooth(), N=32, L=0.02)
+    n, w = _perturbed(col, 9)
+    seen = []
+
+    def hook(f):
+        seen.append(f.copy())
+        return 1.0 + 0.1 * np.tanh(f[:, 3] / np.abs(f[:, 3]).max()), np.full(f.shape[0], 1.2)
+
+    col.multipliers = hook
+    for k in range(3):
+        n, w = F.step(col, n, w)
+        d = col.diag
+        feats = np.stack([d["nf"], 1.5 * d["Tf"], d["E"], d["dn"], 1.5 * d["dT"]], axis=1)
+        assert np.array_equal(seen[k], feats)
+    assert len(seen) == 3 and col.m[1].max() == 1.2

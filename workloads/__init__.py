@@ -206,6 +206,19 @@ def fluid_table_flat(Ngas: float = 3.2e22, nu_w: float = 1.0e5, D_eps_ratio: flo
     return t
 
 
+def fluid_table_ne():
+    """Two-term table of the synthetic neon cross sections (the striated
+    column's gas) on the fluid grid, written by make_fluid_table.py (E/N
+    0.1-300 Td; below the lowest solved temperature, 0.87 eV, the first
+    solved row)."""
+    import json
+    import os
+    with open(os.path.join(os.path.dirname(os.path.abspath(__file__)), "fluid_table_ne_1torr.json")) as f:
+        d = json.load(f)
+    assert d["T_min"] == FLUID_T_MIN and d["T_step"] == FLUID_T_STEP
+    return np.asarray(d["table"], dtype=np.float64)
+
+
 def fluid_table_smooth():
     """Smooth synthetic temperature dependence of the right orders of magnitude
     for a rare gas (mobility falling and diffusion rising with T, Arrhenius
