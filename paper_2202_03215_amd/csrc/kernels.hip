@@ -445,15 +445,9 @@ __device__ __forceinline__ void push_e_chunk(const Params& P, const Soa& sp, int
     chunk_range(n, kb, nb, beg, end);
     if (beg >= end) return;
 
-    for (int k = threadIdx.x; k < kWindow; k += kAdvBlock) win[k] = 0ull;
-    if (threadIdx.x == 0) ncand = 0;
-    double f0;
-    const int wbase = cell_frac(P, sp.x[beg], f0) - kHalo;
-    __syncthreads();
-    const double* __restrict__ E = P.E;
-    uint32_t* __restrict__ cl = P.cand + beg;   // this block's candidate segment
-    uint2* __restrict__ cw = P.cand_w + beg;
-    // software pipeline: the next tile's loads are issued before this tile's work
+    // software pipeline: the next tile's loads are issued before this tile's
+    // work, the first tile's before the block sets up its deposit window
+    // (their latency overlaps that of the window's anchor)
     double px = 0.0, pvx = 0.0;
     uint32_t pid = 0;
     const uint32_t ue = uint32_t(end);
@@ -465,6 +459,14 @@ __device__ __forceinline__ void push_e_chunk(const Params& P, const Soa& sp, int
             pid = ld32(sp.id, i);
         }
     }
+    for (int k = threadIdx.x; k < kWindow; k += kAdvBlock) win[k] = 0ull;
+    if (threadIdx.x == 0) ncand = 0;
+    double f0;
+    const int wbase = cell_frac(P, sp.x[beg], f0) - kHalo;
+    __syncthreads();
+    const double* __restrict__ E = P.E;
+    uint32_t* __restrict__ cl = P.cand + beg;   // this block's candidate segment
+    uint2* __restrict__ cw = P.cand_w + beg;
     int64_t cur = 0;   // this lane's v_x sum (external circuit)
     for (uint32_t i0 = uint32_t(beg); i0 < ue; i0 += kAdvBlock) {
         const uint32_t i = i0 + threadIdx.x;
