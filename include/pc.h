@@ -265,8 +265,8 @@ pc_status pc_batch_step(pc_batch_handle b, int64_t n_steps);
 pc_status pc_batch_column(pc_batch_handle b, int32_t column, pc_handle* out);
 
 /* Autotuner: times trial_steps real steps for each chunk size in {1024,
- * 2048, 4096, 8192} and sort interval in {10, 20, 40, 80}, keeps the fastest
- * (blocking).  No setting changes any result. */
+ * 2048, 3072, 4096, 6144, 8192} and sort interval in {10, 20, 40, 80}, keeps
+ * the fastest (blocking).  No setting changes any result. */
 pc_status pc_batch_tune(pc_batch_handle b, int32_t trial_steps, pc_tuning* out);
 pc_status pc_batch_get_tuning(pc_batch_handle b, pc_tuning* out);
 /* chunk >= 256 particles per workgroup; sort_interval >= 0 */

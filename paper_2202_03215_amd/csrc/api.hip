@@ -1363,7 +1363,7 @@ pc_status pc_batch_set_tuning(pc_batch_handle b, int32_t chunk, int32_t sort_int
 pc_status pc_batch_tune(pc_batch_handle b, int32_t trial_steps, pc_tuning* out)
 {
     if (!b || trial_steps < 1) return fail(PC_ERR_INVALID_ARG, "bad tuning arguments");
-    static const int chunks[] = {1024, 2048, 4096, 8192};
+    static const int chunks[] = {1024, 2048, 3072, 4096, 6144, 8192};
     static const int sorts[] = {10, 20, 40, 80};
     hipEvent_t e0, e1;
     HIPCHK(hipEventCreate(&e0));
@@ -1371,7 +1371,7 @@ pc_status pc_batch_tune(pc_batch_handle b, int32_t trial_steps, pc_tuning* out)
     double best = 1e300;
     int bc = b->chunk, bk = b->K;
     pc_status s = PC_OK;
-    for (int ci = 0; ci < 4 && s == PC_OK; ++ci)
+    for (int ci = 0; ci < int(sizeof(chunks) / sizeof(chunks[0])) && s == PC_OK; ++ci)
         for (int ki = -1; ki < 4 && s == PC_OK; ++ki) {
             if ((s = pc_batch_set_tuning(b, chunks[ci], sorts[ki < 0 ? 0 : ki])) != PC_OK) break;
             hipError_t e = hipEventRecord(e0, b->st);

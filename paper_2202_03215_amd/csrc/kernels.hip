@@ -554,6 +554,54 @@ __device__ __forceinline__ void push_e_chunk(const Params& P, const Soa& sp, int
 }
 
 // -------------------------------------------------------------- ion advance
+// Charge-exchange candidates (u0 < P_cx) are listed during the streaming
+// pass and exchanged in a second phase of the same block, with every lane
+// busy: a candidate (P_cx well below 1 %) would otherwise hold its whole wave
+// through the Maxwellian draw.  The exchange changes only velocities, so the
+// pass's deposit is final.
+__device__ __forceinline__ void list_candidate(bool cand, int* ncand, uint32_t* __restrict__ cl,
+                                               uint2* __restrict__ cw, uint32_t i, uint2 wcd)
+{
+    const uint64_t m = __ballot(cand);
+    if (m == 0) return;
+    const int leader = __ffsll((unsigned long long)m) - 1;
+    int base = 0;
+    if (lane_id() == leader) base = atomicAdd(ncand, __popcll((unsigned long long)m));
+    base = __shfl(base, leader);
+    if (cand) {
+        const uint32_t q = uint32_t(base) + lanes_below(m);
+        st32(cl, q, i);
+        st32(cw, q, wcd);
+    }
+}
+
+// One charge-exchange candidate: a Maxwellian atom velocity a (three
+// normals of the ion's step stream), accepted with probability g / g_cap for
+// the relative speed g; the ion takes a.
+template <bool EV, class St>
+__device__ __forceinline__ void exchange_one(const Params& P, const St& sp, uint8_t* __restrict__ ev,
+                                             int64_t evlen, uint32_t step, bool act, uint32_t i, uint2 wcd)
+{
+    if (!act) return;
+    const uint32_t id = sp.id[i];
+    const double u1 = unif52(wcd.x, wcd.y);
+    double vx, vy, vz;
+    load_v(P, sp, i, kIon, vx, vy, vz);
+    WordStream ws(id, step, kStreamIonStep, P.key0, P.key1);
+    double g0, g1, g2;
+    normal3(ws, g0, g1, g2);
+    const double ax = P.sig_a * g0, ay = P.sig_a * g1, az = P.sig_a * g2;
+    const double dx = vx - ax, dy = vy - ay, dz = vz - az;
+    const double g = sqrt((dx * dx + dy * dy) + dz * dz);
+    if (g > P.g_cap) set_err(P, kErrGCap);
+    uint8_t code = kEvNull;
+    if (u1 * P.g_cap < g) {
+        code = kEvCX;
+        store_v(P, sp, i, kIon, ax, ay, az);
+    }
+    if (EV && int64_t(id) < evlen) ev[id] = code;
+}
+
 // Ions on subcycle steps (dt_i = S dt): gather, push, boundary, radial sink,
 // charge exchange with a Maxwellian atom (null-collision bound Ng sigma g_cap,
 // accepted with g / g_cap, the ion takes the atom's velocity), deposit.
@@ -562,6 +610,7 @@ __device__ __forceinline__ void advance_i_chunk(const Params& P, const Soa& sp, 
                                                 uint8_t* __restrict__ ev, int64_t evlen, int kb, int nb)
 {
     __shared__ unsigned long long win[kWindow];
+    __shared__ int ncand;
     const int64_t n = P.cnt->n[kIon];
     const uint32_t step = uint32_t(P.cnt->step);
     const uint64_t kw = sink_threshold(P, kIon);
@@ -570,18 +619,22 @@ __device__ __forceinline__ void advance_i_chunk(const Params& P, const Soa& sp, 
     if (beg >= end) return;
 
     for (int k = threadIdx.x; k < kWindow; k += kAdvBlock) win[k] = 0ull;
+    if (threadIdx.x == 0) ncand = 0;
     double f0;
     const int wbase = cell_frac(P, sp.x[beg], f0) - kHalo;
     __syncthreads();
     const double* __restrict__ E = P.E;
+    uint32_t* __restrict__ cl = P.cand + beg;   // this block's candidate segment
+    uint2* __restrict__ cw = P.cand_w + beg;
 
     int64_t cur = 0;   // this lane's v_x sum (external circuit)
     for (int64_t i0 = beg; i0 < end; i0 += kAdvBlock) {
         const int64_t i = i0 + threadIdx.x;
         const bool act = i < end;
-        bool alive = false;
+        bool alive = false, cand = false;
         int jn = 0;
         int64_t an = 0;
+        uint2 wcd = make_uint2(0u, 0u);
         double vpush = 0.0;   // v_x after the push, before charge exchange
         if (act) {
             double x = sp.x[i];
@@ -598,28 +651,13 @@ __device__ __forceinline__ void advance_i_chunk(const Params& P, const Soa& sp, 
             if (alive) {
                 const U4 w = philox10(id, step, 0u, kStreamIonStep, P.key0, P.key1);
                 const uint64_t k0 = draw52(w.a, w.b);
-                const double u1 = unif52(w.c, w.d);
                 if (k0 >= kw) {
                     alive = false;
                     code = kEvWall;
-                } else if (k0 < P.kcx) {
-                    const double2 vt = sp.vt[i];
-                    const double vy = vt.x, vz = vt.y;
-                    WordStream ws(id, step, kStreamIonStep, P.key0, P.key1);
-                    double g0, g1, g2;
-                    normal3(ws, g0, g1, g2);
-                    const double ax = P.sig_a * g0, ay = P.sig_a * g1, az = P.sig_a * g2;
-                    const double dx = vx - ax, dy = vy - ay, dz = vz - az;
-                    const double g = sqrt((dx * dx + dy * dy) + dz * dz);
-                    if (g > P.g_cap) set_err(P, kErrGCap);
-                    if (u1 * P.g_cap < g) {
-                        code = kEvCX;
-                        vx = ax;
-                        sp.vt[i] = make_double2(ay, az);
-                    } else {
-                        code = kEvNull;
-                    }
+                } else {
+                    cand = k0 < P.kcx;
                 }
+                wcd = make_uint2(w.c, w.d);
             }
             if (alive) {
                 sp.x[i] = x;
@@ -628,13 +666,14 @@ __device__ __forceinline__ void advance_i_chunk(const Params& P, const Soa& sp, 
                 jn = cell_frac(P, x, fn);
                 an = frac_units(fn);
             }
-            if (EV && int64_t(id) < evlen) ev[id] = code;
+            if (EV && !cand && int64_t(id) < evlen) ev[id] = code;
         }
         const int64_t hp = wave_append(act && !alive, &P.cnt->nh[kIon]);
         if (hp >= 0) {
             if (hp < P.max_holes) P.holes[kIon][hp] = uint32_t(i);
             else set_err(P, kErrLosses);
         }
+        list_candidate(cand, &ncand, cl, cw, uint32_t(i), wcd);
         if (P.circuit && alive) cur += vunits(vpush);
         deposit_wave(P, win, wbase, rho, alive, jn, an);
     }
@@ -646,6 +685,12 @@ __device__ __forceinline__ void advance_i_chunk(const Params& P, const Soa& sp, 
             const int node = wbase + k;
             if (node >= 0 && node < P.nn) atomicAdd((unsigned long long*)&rho[node], v);
         }
+    }
+    // phase 2: this block's charge-exchange candidates
+    const int nc = ncand;
+    for (int k0 = 0; k0 < nc; k0 += kAdvBlock) {
+        const int k = k0 + int(threadIdx.x);
+        exchange_one<EV>(P, sp, ev, evlen, step, k < nc, k < nc ? cl[k] : 0u, k < nc ? cw[k] : make_uint2(0u, 0u));
     }
 }
 
@@ -812,6 +857,7 @@ __device__ __forceinline__ void advance_i_chunk(const Params& P, const Soa32& sp
                                                 uint8_t* __restrict__ ev, int64_t evlen, int kb, int nb)
 {
     __shared__ unsigned long long win[kWindow];
+    __shared__ int ncand;
     const int64_t n = P.cnt->n[kIon];
     const uint32_t step = uint32_t(P.cnt->step);
     const uint64_t kw = sink_threshold(P, kIon);
@@ -819,15 +865,19 @@ __device__ __forceinline__ void advance_i_chunk(const Params& P, const Soa32& sp
     chunk_range(n, kb, nb, beg, end);
     if (beg >= end) return;
     for (int k = threadIdx.x; k < kWindow; k += kAdvBlock) win[k] = 0ull;
+    if (threadIdx.x == 0) ncand = 0;
     const int wbase = sp.cell[beg] - kHalo;
     __syncthreads();
+    uint32_t* __restrict__ cl = P.cand + beg;   // this block's candidate segment
+    uint2* __restrict__ cw = P.cand_w + beg;
     int64_t cur = 0;   // this lane's v_x sum (external circuit)
     for (int64_t i0 = beg; i0 < end; i0 += kAdvBlock) {
         const int64_t i = i0 + threadIdx.x;
         const bool act = i < end;
-        bool alive = false;
+        bool alive = false, cand = false;
         int jn = 0;
         int64_t an = 0;
+        uint2 wcd = make_uint2(0u, 0u);
         float upush = 0.0f;   // v_x after the push, before charge exchange
         if (act) {
             int c = sp.cell[i];
@@ -843,27 +893,10 @@ __device__ __forceinline__ void advance_i_chunk(const Params& P, const Soa32& sp
                 if (k0 >= kw) {
                     alive = false;
                     code = kEvWall;
-                } else if (k0 < P.kcx) {
-                    const double u1 = unif52(w.c, w.d);
-                    const double vx = double(u) * P.u2v_i;
-                    const float2 vt = sp.vt[i];
-                    const double vy = double(vt.x) * P.u2v_i;
-                    const double vz = double(vt.y) * P.u2v_i;
-                    WordStream ws(id, step, kStreamIonStep, P.key0, P.key1);
-                    double g0, g1, g2;
-                    normal3(ws, g0, g1, g2);
-                    const double ax = P.sig_a * g0, ay = P.sig_a * g1, az = P.sig_a * g2;
-                    const double dx = vx - ax, dy = vy - ay, dz = vz - az;
-                    const double g = sqrt((dx * dx + dy * dy) + dz * dz);
-                    if (g > P.g_cap) set_err(P, kErrGCap);
-                    if (u1 * P.g_cap < g) {
-                        code = kEvCX;
-                        u = float(ax / P.u2v_i);
-                        sp.vt[i] = make_float2(float(ay / P.u2v_i), float(az / P.u2v_i));
-                    } else {
-                        code = kEvNull;
-                    }
+                } else {
+                    cand = k0 < P.kcx;
                 }
+                wcd = make_uint2(w.c, w.d);
             }
             if (alive) {
                 sp.cell[i] = c;
@@ -872,13 +905,14 @@ __device__ __forceinline__ void advance_i_chunk(const Params& P, const Soa32& sp
                 jn = c;
                 an = frac_units32(off);
             }
-            if (EV && int64_t(id) < evlen) ev[id] = code;
+            if (EV && !cand && int64_t(id) < evlen) ev[id] = code;
         }
         const int64_t hp = wave_append(act && !alive, &P.cnt->nh[kIon]);
         if (hp >= 0) {
             if (hp < P.max_holes) P.holes[kIon][hp] = uint32_t(i);
             else set_err(P, kErrLosses);
         }
+        list_candidate(cand, &ncand, cl, cw, uint32_t(i), wcd);
         if (P.circuit && alive) cur += vunits(double(upush) * P.u2v_i);
         deposit_wave(P, win, wbase, rho, alive, jn, an);
     }
@@ -890,6 +924,12 @@ __device__ __forceinline__ void advance_i_chunk(const Params& P, const Soa32& sp
             const int node = wbase + k;
             if (node >= 0 && node < P.nn) atomicAdd((unsigned long long*)&rho[node], v);
         }
+    }
+    // phase 2: this block's charge-exchange candidates
+    const int nc = ncand;
+    for (int k0 = 0; k0 < nc; k0 += kAdvBlock) {
+        const int k = k0 + int(threadIdx.x);
+        exchange_one<EV>(P, sp, ev, evlen, step, k < nc, k < nc ? cl[k] : 0u, k < nc ? cw[k] : make_uint2(0u, 0u));
     }
 }
 
