@@ -51,6 +51,7 @@ class Column:
                                        C.c_void_p(self.stream.cuda_stream), C.byref(h)))
         self.h = h
         self._events = None
+        self._destroy = N.lib().pc_destroy   # held: module globals may be gone at interpreter exit
 
     @classmethod
     def _member(cls, owner: "Batch", index: int, cfg: dict) -> "Column":
@@ -76,8 +77,9 @@ class Column:
         if getattr(self, "_owner", None) is not None:
             return   # batch members are freed with their batch
         h = getattr(self, "h", None)
-        if h is not None and h.value:
-            N.lib().pc_destroy(h)
+        destroy = getattr(self, "_destroy", None)
+        if h is not None and h.value and destroy is not None:
+            destroy(h)
             self.h = None
 
     # ------------------------------------------------------- stream order
@@ -233,14 +235,16 @@ class Batch:
                                       C.c_void_p(self.stream.cuda_stream), C.byref(h)))
         self.h = h
         self._views = {}
+        self._destroy = N.lib().pc_batch_destroy   # held: module globals may be gone at interpreter exit
 
     def __len__(self) -> int:
         return len(self.cfgs)
 
     def __del__(self):
         h = getattr(self, "h", None)
-        if h is not None and h.value:
-            N.lib().pc_batch_destroy(h)
+        destroy = getattr(self, "_destroy", None)
+        if h is not None and h.value and destroy is not None:
+            destroy(h)
             self.h = None
 
     def column(self, c: int) -> Column:

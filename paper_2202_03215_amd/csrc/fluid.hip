@@ -28,7 +28,7 @@
 
 namespace pcfluid {
 
-constexpr int kFaceBlock = 256;
+constexpr int kFaceBlock = 1024;   // 16 waves per column: the face loop is latency-bound
 constexpr int kSolveBlock = 1024;
 constexpr int kMaxCells = 4096;
 constexpr int kCols = 6;   // table columns

@@ -91,11 +91,13 @@ class FluidBatch:
                                     C.byref(h)))
         self.h = h
         self._net = None
+        self._destroy = _lib().pc_fluid_destroy   # held: module globals may be gone at interpreter exit
 
     def __del__(self):
         h = getattr(self, "h", None)
-        if h is not None and h.value:
-            _lib().pc_fluid_destroy(h)
+        destroy = getattr(self, "_destroy", None)
+        if h is not None and h.value and destroy is not None:
+            destroy(h)
             self.h = None
 
     def set_state(self, n, w) -> None:
