@@ -52,8 +52,10 @@ WORKLOADS = {
     "small_bounded": lambda: W.small_bounded(),
 }
 
-# sources of the particle kernels: a counter profile is valid for the build it was taken on
-KERNEL_SOURCES = ("paper_2202_03215_amd/csrc/kernels.hip", "paper_2202_03215_amd/csrc/device.h")
+# sources and build flags of the particle kernels: a counter profile is valid
+# for the build it was taken on
+KERNEL_SOURCES = ("paper_2202_03215_amd/csrc/kernels.hip", "paper_2202_03215_amd/csrc/device.h",
+                  "paper_2202_03215_amd/build.py")
 
 
 def kernel_source_sha16() -> str:

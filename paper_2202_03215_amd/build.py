@@ -1,7 +1,10 @@
 """Compile the gfx950 HIP library (libpc.so) in-tree with hipcc.
 
 Flags: no FMA contraction (every product and sum rounded separately, so the
-particle arithmetic is reproducible), no packed-FP32 instructions, -O3.
+particle arithmetic is reproducible), no packed-FP32 instructions, -O3, and
+no compiler rewriting of atomics into wave-level aggregates (the kernels
+aggregate their atomics themselves, mostly from one lane; the rewrite added
+a third of the electron push's instructions).
 """
 import os
 import shutil
@@ -27,6 +30,7 @@ def build(verbose: bool = False) -> str:
     cmd = [hipcc(), "--offload-arch=gfx950", "-O3", "-std=c++17", "-ffp-contract=off",
            "-fno-fast-math", "-fPIC", "-shared",
            "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+           "-mllvm", "-amdgpu-atomic-optimizer-strategy=None",
            "-I", os.path.join(ROOT, "include"), "-o", tmp]
     cmd += [os.path.join(HERE, s) for s in SOURCES]
     if verbose:
