@@ -66,12 +66,14 @@ def kernel_source_sha16() -> str:
     return h.hexdigest()[:16]
 
 
-def counter_traffic(workload: str, precision: str) -> tuple:
+def counter_traffic(workload: str, precision: str, electrons: float = 0.0) -> tuple:
     """HBM bytes per launch of the electron advance kernel from the committed
     counter profile (profiles/hbm_counters_push_<workload>_<precision>.md):
     FETCH_SIZE and WRITE_SIZE per dispatch, each scaled by what the same
-    counter reads for the stream-probe copy of known size.  Null when there
-    is no profile or when it was taken on other kernel sources."""
+    counter reads for the stream-probe copy of known size, and by the ratio
+    of this run's electrons per launch to the profile run's when the record
+    holds that count.  Null when there is no profile or when it was taken on
+    other kernel sources or build flags."""
     path = os.path.join(ROOT, "profiles", f"hbm_counters_push_{workload}_{precision}.md")
     if not os.path.exists(path):
         return None, f"no counter profile for {workload} {precision}"
@@ -83,7 +85,11 @@ def counter_traffic(workload: str, precision: str) -> tuple:
         return None, (f"{os.path.relpath(path, ROOT)} was taken on kernel sources {rec.get('source_sha16')}, "
                       f"not the current {kernel_source_sha16()}")
     t = rec["fetch_kib"] * 1024.0 * rec["fetch_factor"] + rec["write_kib"] * 1024.0 * rec["write_factor"]
-    return t, f"{os.path.relpath(path, ROOT)} (kernel sources {rec['source_sha16']})"
+    note = f"{os.path.relpath(path, ROOT)} (kernel sources {rec['source_sha16']})"
+    if electrons > 0 and rec.get("electrons_per_launch"):
+        t *= electrons / float(rec["electrons_per_launch"])
+        note += f", scaled from {rec['electrons_per_launch']:.0f} to {electrons:.0f} electrons per launch"
+    return t, note
 
 
 def electron_bytes_per_step(p_null: float, fp32: bool = False) -> float:
@@ -207,7 +213,7 @@ def measure(cfg: dict, args, tag: str, workload: str) -> dict:
     print(f"[bench] {tag}: {args.steps} steps in {elapsed:.4f} s (graphs), {t3 - t2:.4f} s (eager, "
           f"timed); push kernel avg {avg_s * 1e6:.2f} us over {launches} launches",
           file=sys.stderr, flush=True)
-    traffic, tnote = counter_traffic(workload, "fp32" if fp32 else "fp64")
+    traffic, tnote = counter_traffic(workload, "fp32" if fp32 else "fp64", ne_avg2)
     moments_us = None
     if args.moments:
         # diagnostics on demand (cell moments of both species and the EEPF

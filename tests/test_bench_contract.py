@@ -80,3 +80,19 @@ def test_json_line(torch_cuda, monkeypatch, capsys):
     p = d["stream_probe"]
     assert p["copy_ok"] and p["GB_s"] > 0
     assert abs(r["frac_of_measured_copy"] - r["achieved"] / p["GB_s"]) <= 1e-12
+
+
+def test_counter_traffic_scales_with_electrons(tmp_path, monkeypatch):
+    (tmp_path / "profiles").mkdir()
+    for f in bench.KERNEL_SOURCES:
+        os.makedirs(tmp_path / os.path.dirname(f), exist_ok=True)
+        with open(os.path.join(bench.ROOT, f), "rb") as src, open(tmp_path / f, "wb") as dst:
+            dst.write(src.read())
+    monkeypatch.setattr(bench, "ROOT", str(tmp_path))
+    rec = dict(source_sha16=bench.kernel_source_sha16(), fetch_kib=1000.0, write_kib=500.0, fetch_factor=2.0,
+               write_factor=1.0, electrons_per_launch=4.0e6)
+    body = "```json\n" + json.dumps(rec) + "\n```\n"
+    (tmp_path / "profiles" / "hbm_counters_push_column_50cm_fp64.md").write_text(body)
+    t0, _ = bench.counter_traffic("column_50cm", "fp64")
+    t1, note = bench.counter_traffic("column_50cm", "fp64", 5.0e6)
+    assert t0 == 2500.0 * 1024.0 and abs(t1 / t0 - 1.25) < 1e-12 and "scaled" in note
