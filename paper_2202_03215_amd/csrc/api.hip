@@ -938,9 +938,12 @@ pc_status pc_timer_enable(pc_handle h, int64_t max_launches)
     for (hipEvent_t e : h->tev) HIPCHK(hipEventDestroy(e));
     h->tev.clear();
     h->tcount = 0;
+    // timing only (read after the stream is synchronized): no system-scope
+    // fence, whose cache writeback and invalidation at every recorded event
+    // would slow the timed launch and the work after it
     for (int64_t k = 0; k < 2 * max_launches; ++k) {
         hipEvent_t e;
-        HIPCHK(hipEventCreate(&e));
+        HIPCHK(hipEventCreateWithFlags(&e, hipEventDisableSystemFence));
         h->tev.push_back(e);
     }
     return PC_OK;
@@ -1409,7 +1412,7 @@ pc_status pc_batch_timer_enable(pc_batch_handle b, int64_t max_launches)
     b->tcount = 0;
     for (int64_t k = 0; k < 2 * max_launches; ++k) {
         hipEvent_t e;
-        HIPCHK(hipEventCreate(&e));
+        HIPCHK(hipEventCreateWithFlags(&e, hipEventDisableSystemFence));   // timing only, as above
         b->tev.push_back(e);
     }
     return PC_OK;
