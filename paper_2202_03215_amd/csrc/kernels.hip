@@ -1399,18 +1399,33 @@ __device__ void pair_victims(const Params& P, const St& se, const St& si, int64_
 constexpr int kRoleBoth = 0, kRoleField = 1, kRoleParticles = 2;
 constexpr uint32_t kLoadedSpinMax = 1u << 22;   // s_sleep rounds before giving up (about 0.2 s)
 
-__device__ __forceinline__ void post_field_loaded(const Params& P, int64_t step_in)
+// The flag orders reads before writes only: the field half's charge loads
+// must have returned before the particle half's first add to the same arrays.
+// The field half writes nothing before the flag that the particle half
+// reads, so neither side needs a device-scope release or acquire (on this
+// part the release writes back the XCD's L2 -- much of it dirty with the
+// push's particle stores -- and each acquiring poll invalidates it).  The
+// field half waits for its own loads by handing their values to an empty asm
+// statement, the block barrier waits for every wave, and the flag is a
+// relaxed device-scope store, coherent across XCDs.  The particle half polls
+// with relaxed device-scope loads; its adds are issued after its barrier,
+// which follows the poll that saw the flag.
+__device__ __forceinline__ void post_field_loaded(const Params& P, int64_t step_in, const FieldPre* fp)
 {
+    if (fp != nullptr) {
+#pragma unroll
+        for (int k = 0; k < kMaxSeg; ++k) asm volatile("" ::"v"(fp->q[k]));
+    }
     __syncthreads();   // every thread of the field half holds its charges
     if (threadIdx.x == 0)
-        __hip_atomic_store(&P.cnt->field_loaded, step_in + 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_store(&P.cnt->field_loaded, step_in + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 __device__ __forceinline__ void wait_field_loaded(const Params& P, int64_t step_in)
 {
     if (threadIdx.x == 0) {
         for (uint32_t it = 0;; ++it) {
-            if (__hip_atomic_load(&P.cnt->field_loaded, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == step_in + 1)
+            if (__hip_atomic_load(&P.cnt->field_loaded, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == step_in + 1)
                 break;
             if (it == kLoadedSpinMax) {   // never expected: flag the step's field as suspect
                 set_err(P, kErrField);
@@ -1446,8 +1461,9 @@ __device__ __forceinline__ void finish_column(const Params& P, const St& se, con
     const int64_t nb_in = cnt->nb;
     const int64_t step_in = cnt->step;
     FieldPre fp;
-    if (do_field && P.poisson && !P.pair) fp = field_prepare(P, field_load(P, rho_e, rho_i));
-    if (role == kRoleField) post_field_loaded(P, step_in);
+    const bool loaded = do_field && P.poisson && !P.pair;
+    if (loaded) fp = field_prepare(P, field_load(P, rho_e, rho_i));
+    if (role == kRoleField) post_field_loaded(P, step_in, loaded ? &fp : nullptr);
     int64_t nb = nb_in < P.max_births ? nb_in : P.max_births;
     int64_t nh[2], Np[2];
     bool lds[2];
@@ -2202,6 +2218,17 @@ __global__ __launch_bounds__(256) void k_sort_scatter(Params P, St src, St dst, 
 // device table; a launch over particle chunks takes its (column, chunk) from
 // an item table ordered by column, and the per-column single-workgroup work
 // (field, births, losses, sort scan) runs as one workgroup per column.
+// The column table is written by the host between launches and only read by
+// the kernels, so it is read through the constant address space: the
+// compiler then knows that the pointers it holds address global memory and
+// emits global loads and stores for them.  Through a plain pointer they would
+// be generic (flat) accesses, which also count against the LDS wait counter,
+// so that every LDS wait would wait for the outstanding memory operations too.
+typedef const __attribute__((address_space(4))) ColumnDev* ColumnTable;
+__device__ __forceinline__ const ColumnDev& column_of(const ColumnDev* cols, int i)
+{
+    return *(const ColumnDev*)&((ColumnTable)cols)[i];
+}
 template <class St> __device__ __forceinline__ const St& store_of(const ColumnDev& C, int s, int b);
 template <> __device__ __forceinline__ const Soa& store_of<Soa>(const ColumnDev& C, int s, int b)
 {
@@ -2217,7 +2244,7 @@ __global__ __launch_bounds__(kAdvBlock) void k_batch_push_e(const ColumnDev* __r
                                                            const BatchItem* __restrict__ items, BatchStep b)
 {
     const BatchItem it = items[blockIdx.x];
-    const ColumnDev& C = cols[it.col];
+    const ColumnDev& C = column_of(cols, it.col);
     push_e_chunk<false>(C.P, store_of<St>(C, kElectron, b.cur[kElectron]), C.rho[kElectron][b.re_new],
                         nullptr, 0, it.k, it.nk);
 }
@@ -2226,7 +2253,7 @@ __global__ __launch_bounds__(kAdvBlock) void k_batch_advance_i(const ColumnDev* 
                                                               const BatchItem* __restrict__ items, BatchStep b)
 {
     const BatchItem it = items[blockIdx.x];
-    const ColumnDev& C = cols[it.col];
+    const ColumnDev& C = column_of(cols, it.col);
     advance_i_chunk<false>(C.P, store_of<St>(C, kIon, b.cur[kIon]), C.rho[kIon][b.ri_use], nullptr, 0, it.k,
                            it.nk);
 }
@@ -2234,7 +2261,7 @@ template <class St>
 __global__ __launch_bounds__(kOneBlock) void k_batch_finish(const ColumnDev* __restrict__ cols, BatchStep b)
 {
     // two workgroups per column (field half, then particle half)
-    const ColumnDev& C = cols[blockIdx.x >> 1];
+    const ColumnDev& C = column_of(cols, blockIdx.x >> 1);
     finish_column(C.P, store_of<St>(C, kElectron, b.cur[kElectron]), store_of<St>(C, kIon, b.cur[kIon]),
                   C.rho[kElectron][b.re_new], C.rho[kIon][b.ri_use], C.rho[kElectron][b.re_old],
                   b.ri_old >= 0 ? C.rho[kIon][b.ri_old] : nullptr,
@@ -2245,19 +2272,19 @@ __global__ __launch_bounds__(256) void k_batch_sort_count(const ColumnDev* __res
                                                          const BatchItem* __restrict__ items, int S, int cur)
 {
     const BatchItem it = items[blockIdx.x];
-    const ColumnDev& C = cols[it.col];
+    const ColumnDev& C = column_of(cols, it.col);
     sort_count_chunk(C.P, store_of<St>(C, S, cur), S, it.k, it.nk);
 }
 __global__ __launch_bounds__(kOneBlock) void k_batch_sort_scan(const ColumnDev* __restrict__ cols)
 {
-    sort_scan_column(cols[blockIdx.x].P);
+    sort_scan_column(column_of(cols, blockIdx.x).P);
 }
 template <class St>
 __global__ __launch_bounds__(256) void k_batch_sort_scatter(const ColumnDev* __restrict__ cols,
                                                            const BatchItem* __restrict__ items, int S, int cur)
 {
     const BatchItem it = items[blockIdx.x];
-    const ColumnDev& C = cols[it.col];
+    const ColumnDev& C = column_of(cols, it.col);
     sort_scatter_chunk(C.P, store_of<St>(C, S, cur), store_of<St>(C, S, 1 - cur), S, it.k, it.nk);
 }
 
