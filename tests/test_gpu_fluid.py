@@ -1,7 +1,9 @@
 """Batched fluid column on the GPU against the FP64 fluid oracle.
 
 - cyclic tridiagonal solve (cyclic reduction in LDS, FP64) against a sparse
-  LU solve: residual-level agreement (<= 1e-12 relative);
+  LU solve: residual-level agreement (<= 1e-12 relative), on random
+  diagonally dominant systems and on weakly dominant backward-Euler
+  diffusion systems (r = 50);
 - one step from a shared state, table closure: FP32 state and fluxes, FP64
   solves.  The differences come from FP32 rounding of the explicit terms
   (single precision, 6e-8, amplified by differences such as Phi_{j+1} -
@@ -30,15 +32,22 @@ def torch_cuda():
     return torch
 
 
-@pytest.mark.parametrize("n", [64, 1024, 4096])
-def test_cyclic_tridiagonal_solve(torch_cuda, n):
+@pytest.mark.parametrize("n,weak", [(8, False), (32, False), (64, False), (128, True), (1024, False),
+                                    (4096, False), (4096, True)])
+def test_cyclic_tridiagonal_solve(torch_cuda, n, weak):
     from paper_2202_03215_amd.fluid import cyclic_tridiag
     torch = torch_cuda
     rng = np.random.default_rng(n)
     ns = 3
-    a = -rng.random((ns, n))
-    c = -rng.random((ns, n))
-    b = 1.0 + np.abs(a) + np.abs(c) + rng.random((ns, n))
+    if weak:   # backward-Euler diffusion at r = 50: 1 + r (D_- + D_+) on the diagonal
+        D = 0.5 + rng.random((ns, n))
+        a = -50.0 * np.roll(D, 1, axis=1)
+        c = -50.0 * D
+        b = 1.0 - a - c
+    else:
+        a = -rng.random((ns, n))
+        c = -rng.random((ns, n))
+        b = 1.0 + np.abs(a) + np.abs(c) + rng.random((ns, n))
     d = rng.normal(size=(ns, n))
     x = cyclic_tridiag(*(torch.from_numpy(v).cuda() for v in (a, b, c, d))).cpu().numpy()
     for s in range(ns):
