@@ -18,7 +18,7 @@
  * T >= T_min.  State and fluxes in FP32, the two cyclic tridiagonal systems
  * per column and step in FP64 (cyclic reduction in LDS).
  *
- * Table: table_len rows on T_k = T_min + k T_step [eV], 6 columns:
+ * Table: table_len rows (2..1024) on T_k = T_min + k T_step [eV], 6 columns:
  *   mu_e N [1/(V m s)], D_e N [1/(m s)], mu_eps N, D_eps N, k_iz [m^3/s]
  *   (nu_i = N k_iz), L/N [eV m^3/s] (collisional energy loss per electron).
  * State: n [m^-3] and w = 3/2 n T [eV m^-3], device float [n_columns][n_cells].

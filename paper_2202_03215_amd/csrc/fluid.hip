@@ -32,6 +32,8 @@ constexpr int kFaceBlock = 1024;   // 16 waves per column: the face loop is late
 constexpr int kSolveBlock = 1024;
 constexpr int kMaxCells = 4096;
 constexpr int kCols = 6;   // table columns
+constexpr int kMaxTableRows = 1024;   // the table is staged in LDS by both kernels (24 KB)
+constexpr int kFacesPerThread = kMaxCells / kFaceBlock;
 
 struct ColDev {
     double L, Ngas, E0, nu_w, muiN;
@@ -59,7 +61,8 @@ struct Coef {
     float s[kCols];
 };
 
-__device__ __forceinline__ Coef interp(const Globals& G, float T)
+// tab: the workgroup's LDS copy of the table (stage_table)
+__device__ __forceinline__ Coef interp(const Globals& G, const float* tab, float T)
 {
     const float Tmax = G.T_min + float(G.K - 1) * G.T_step;
     const float Tc = fminf(fmaxf(T, G.T_min), Tmax);
@@ -69,7 +72,7 @@ __device__ __forceinline__ Coef interp(const Globals& G, float T)
     if (k < 0) k = 0;
     const float f = u - float(k);
     Coef c;
-    const float* lo = G.table + k * kCols;
+    const float* lo = tab + k * kCols;
     const float* hi = lo + kCols;
 #pragma unroll
     for (int q = 0; q < kCols; ++q) {
@@ -78,6 +81,14 @@ __device__ __forceinline__ Coef interp(const Globals& G, float T)
         c.s[q] = d / G.T_step;
     }
     return c;
+}
+
+// the table into LDS: a face needs three interpolations, each a dependent
+// gather of twelve coefficients
+__device__ __forceinline__ void stage_table(const Globals& G, float* tab)
+{
+    for (int k = threadIdx.x; k < G.K * kCols; k += blockDim.x) tab[k] = G.table[k];
+    __syncthreads();
 }
 
 __device__ __forceinline__ double block_sum_d(double v, double* sh)
@@ -107,8 +118,8 @@ __device__ __forceinline__ void face_multipliers(const Globals& G, int64_t f, fl
     }
 }
 
-__device__ __forceinline__ FaceQ face(const Globals& G, const ColDev& C, const float* n, const float* w, int j,
-                                      float mD, float mE)
+__device__ __forceinline__ FaceQ face(const Globals& G, const float* tab, const ColDev& C, const float* n,
+                                      const float* w, int j, float mD, float mE)
 {
     const int N = G.N;
     const int jr = (j + 1) & (N - 1);
@@ -116,7 +127,7 @@ __device__ __forceinline__ FaceQ face(const Globals& G, const ColDev& C, const f
     const float dx = float(C.L / double(N));
     const float n0 = n[j], n1 = n[jr];
     const float T0 = w[j] / (1.5f * n0), T1 = w[jr] / (1.5f * n1);
-    const Coef c0 = interp(G, T0), c1 = interp(G, T1);
+    const Coef c0 = interp(G, tab, T0), c1 = interp(G, tab, T1);
     const float Phi0 = n0 * (c0.v[1] / Ng) / (c0.v[0] / Ng);
     const float Phi1 = n1 * (c1.v[1] / Ng) / (c1.v[0] / Ng);
     FaceQ q;
@@ -124,7 +135,7 @@ __device__ __forceinline__ FaceQ face(const Globals& G, const ColDev& C, const f
     q.Tf = 0.5f * (T0 + T1);
     q.dn = (n1 - n0) / dx;
     q.dT = (T1 - T0) / dx;
-    const Coef cf = interp(G, q.Tf);
+    const Coef cf = interp(G, tab, q.Tf);
     q.mue = cf.v[0] / Ng;
     q.De = mD * (cf.v[1] / Ng);
     q.mueps = mE * (cf.v[2] / Ng);
@@ -140,28 +151,38 @@ __device__ __forceinline__ FaceQ face(const Globals& G, const ColDev& C, const f
 __global__ __launch_bounds__(kFaceBlock) void k_fluid_faces(Globals G)
 {
     __shared__ double sh[kFaceBlock / 64];
+    __shared__ float tab[kMaxTableRows * kCols];
     const int col = blockIdx.x;
     const ColDev C = G.cols[col];
     const int N = G.N;
     const float* n = G.n + int64_t(col) * N;
     const float* w = G.w + int64_t(col) * N;
     const int64_t o = int64_t(col) * N;
+    stage_table(G, tab);
+    // the thread's faces j = tid + r * blockDim.x, kept in registers for the
+    // second pass (Gamma_T needs the column sums of A and B first)
+    FaceQ qs[kFacesPerThread];
     double sa = 0.0, sb = 0.0;
-    for (int j = threadIdx.x; j < N; j += blockDim.x) {
-        float mD, mE;
-        face_multipliers(G, o + j, mD, mE);
-        const FaceQ q = face(G, C, n, w, j, mD, mE);
-        sa += double(q.A);
-        sb += double(q.B);
+#pragma unroll
+    for (int r = 0; r < kFacesPerThread; ++r) {
+        const int j = threadIdx.x + r * kFaceBlock;
+        if (j < N) {
+            float mD, mE;
+            face_multipliers(G, o + j, mD, mE);
+            qs[r] = face(G, tab, C, n, w, j, mD, mE);
+            sa += double(qs[r].A);
+            sb += double(qs[r].B);
+        }
     }
     const double SA = block_sum_d(sa, sh);
     const double SB = block_sum_d(sb, sh);
     const float GT = float((C.E0 + SA / N) / (SB / N));
     const float mui = float(C.muiN / C.Ngas);
-    for (int j = threadIdx.x; j < N; j += blockDim.x) {
-        float mD, mE;
-        face_multipliers(G, o + j, mD, mE);
-        const FaceQ q = face(G, C, n, w, j, mD, mE);
+#pragma unroll
+    for (int r = 0; r < kFacesPerThread; ++r) {
+        const int j = threadIdx.x + r * kFaceBlock;
+        if (j >= N) break;
+        const FaceQ& q = qs[r];
         const float E = -q.A + GT * q.B;
         const float Da = mui * q.De / q.mue;
         const float beta = 1.5f * q.Tf * q.mueps;
@@ -226,6 +247,7 @@ __device__ void cyclic_reduce(double* a, double* b, double* c, double* d, int N)
 __global__ __launch_bounds__(kSolveBlock) void k_fluid_solve(Globals G)
 {
     __shared__ double A[kMaxCells], B[kMaxCells], Cc[kMaxCells], D[kMaxCells];
+    __shared__ float tab[kMaxTableRows * kCols];
     constexpr int kRows = kMaxCells / kSolveBlock;
     const int col = blockIdx.x;
     const ColDev C = G.cols[col];
@@ -237,6 +259,7 @@ __global__ __launch_bounds__(kSolveBlock) void k_fluid_solve(Globals G)
     const double dt = double(G.dt);
     const double r = dt / (dx * dx);
     const float Ng = float(C.Ngas);
+    stage_table(G, tab);
     double rhs_w[kRows];
     // density system and the energy right-hand side (explicit parts)
 #pragma unroll
@@ -258,7 +281,7 @@ __global__ __launch_bounds__(kSolveBlock) void k_fluid_solve(Globals G)
                 hm = G.H[o + jm];
             }
             const float nj = n[j], wj = w[j];
-            const Coef cc = interp(G, wj / (1.5f * nj));
+            const Coef cc = interp(G, tab, wj / (1.5f * nj));
             const float Sn = nj * (Ng * cc.v[4] - float(C.nu_w));
             const float P = -0.5f * (gm * G.E[o + jm] + gp * G.E[o + j]);
             const float Sw = P - nj * (Ng * cc.v[5]);
@@ -353,7 +376,8 @@ pc_status validate(const pc_fluid_config* c)
     if (c->n_columns < 1 || c->n_columns > 65535) return ferr(PC_ERR_INVALID_ARG, "n_columns");
     if (!pow2(c->n_cells) || c->n_cells < 64 || c->n_cells > kMaxCells)
         return ferr(PC_ERR_INVALID_ARG, "n_cells must be a power of two in [64, 4096]");
-    if (c->table_len < 2) return ferr(PC_ERR_INVALID_ARG, "table_len");
+    if (c->table_len < 2 || c->table_len > kMaxTableRows)
+        return ferr(PC_ERR_INVALID_ARG, "table_len must be in [2, 1024]");
     if (!(c->dt > 0.0) || !(c->T_step > 0.0) || !(c->T_min > 0.0) || !(c->n_floor > 0.0))
         return ferr(PC_ERR_INVALID_ARG, "dt, T_min, T_step and n_floor must be positive");
     return PC_OK;
