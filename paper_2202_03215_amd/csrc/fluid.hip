@@ -214,32 +214,60 @@ __global__ __launch_bounds__(kFaceBlock) void k_fluid_faces(Globals G)
 // Level s (1, 2, ..., N/2) eliminates x_{j-s}, x_{j+s} from the equations
 // j = 0 mod 2s using equations j -+ s; the last level leaves one equation in
 // x_0 alone; back substitution then recovers j = s mod 2s from j -+ s.
+// Levels that update more than 64 equations run on the whole workgroup, one
+// block barrier each; the rest, down to x_0 and back, on wave 0 alone: the
+// LDS operations of one wave complete in issue order, so those levels need
+// only compiler ordering.  Every equation sees the same arithmetic in the
+// same order either way.
+__device__ __forceinline__ void lds_wave_order() { asm volatile("" ::: "memory"); }
+
+__device__ __forceinline__ void cr_eliminate(double* a, double* b, double* c, double* d, int N, int s, int j)
+{
+    const int jm = (j - s) & (N - 1), jp = (j + s) & (N - 1);
+    const double al = -a[j] / b[jm];
+    const double ga = -c[j] / b[jp];
+    const double na = al * a[jm];
+    const double nc = ga * c[jp];
+    const double nb = b[j] + al * c[jm] + ga * a[jp];
+    const double nd = d[j] + al * d[jm] + ga * d[jp];
+    a[j] = na;
+    b[j] = nb;
+    c[j] = nc;
+    d[j] = nd;
+}
+
+__device__ __forceinline__ void cr_substitute(const double* a, const double* b, const double* c, double* d, int N,
+                                              int s, int j)
+{
+    const int jm = (j - s) & (N - 1), jp = (j + s) & (N - 1);
+    d[j] = (d[j] - a[j] * d[jm] - c[j] * d[jp]) / b[j];
+}
+
 __device__ void cyclic_reduce(double* a, double* b, double* c, double* d, int N)
 {
-    for (int s = 1; s < N; s <<= 1) {
+    int s = 1;
+    for (; s < N && N / (2 * s) > 64; s <<= 1) {
         __syncthreads();
-        for (int j = threadIdx.x * 2 * s; j < N; j += blockDim.x * 2 * s) {
-            const int jm = (j - s) & (N - 1), jp = (j + s) & (N - 1);
-            const double al = -a[j] / b[jm];
-            const double ga = -c[j] / b[jp];
-            const double na = al * a[jm];
-            const double nc = ga * c[jp];
-            const double nb = b[j] + al * c[jm] + ga * a[jp];
-            const double nd = d[j] + al * d[jm] + ga * d[jp];
-            a[j] = na;
-            b[j] = nb;
-            c[j] = nc;
-            d[j] = nd;
-        }
+        for (int j = threadIdx.x * 2 * s; j < N; j += blockDim.x * 2 * s) cr_eliminate(a, b, c, d, N, s, j);
     }
     __syncthreads();
-    if (threadIdx.x == 0) d[0] = d[0] / (a[0] + b[0] + c[0]);   // x_{-N} = x_N = x_0
-    for (int s = N >> 1; s >= 1; s >>= 1) {
-        __syncthreads();
-        for (int j = s + threadIdx.x * 2 * s; j < N; j += blockDim.x * 2 * s) {
-            const int jm = (j - s) & (N - 1), jp = (j + s) & (N - 1);
-            d[j] = (d[j] - a[j] * d[jm] - c[j] * d[jp]) / b[j];
+    if (threadIdx.x < 64) {
+        for (int t = s; t < N; t <<= 1) {
+            const int j = threadIdx.x * 2 * t;
+            if (j < N) cr_eliminate(a, b, c, d, N, t, j);
+            lds_wave_order();
         }
+        if (threadIdx.x == 0) d[0] = d[0] / (a[0] + b[0] + c[0]);   // x_{-N} = x_N = x_0
+        lds_wave_order();
+        for (int t = N >> 1; t >= s; t >>= 1) {
+            const int j = t + threadIdx.x * 2 * t;
+            if (j < N) cr_substitute(a, b, c, d, N, t, j);
+            lds_wave_order();
+        }
+    }
+    for (int t = s >> 1; t >= 1; t >>= 1) {
+        __syncthreads();
+        for (int j = t + threadIdx.x * 2 * t; j < N; j += blockDim.x * 2 * t) cr_substitute(a, b, c, d, N, t, j);
     }
     __syncthreads();
 }
