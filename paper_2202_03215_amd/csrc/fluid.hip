@@ -34,6 +34,11 @@ constexpr int kMaxCells = 4096;
 constexpr int kCols = 6;   // table columns
 constexpr int kMaxTableRows = 1024;   // the table is staged in LDS by both kernels (24 KB)
 constexpr int kFacesPerThread = kMaxCells / kFaceBlock;
+// LDS rows of the tridiagonal systems: element j at pad(j) = j + j / 32, one
+// spare double per 32, so that the reduction's strided accesses (equations
+// 2s apart at level s) spread over the banks instead of piling onto a few
+constexpr int kPadCells = kMaxCells + kMaxCells / 32;
+__device__ __forceinline__ int pad(int j) { return j + (j >> 5); }
 
 struct ColDev {
     double L, Ngas, E0, nu_w, muiN;
@@ -210,7 +215,8 @@ __global__ __launch_bounds__(kFaceBlock) void k_fluid_faces(Globals G)
 }
 
 // ---- cyclic reduction for a_j x_{j-1} + b_j x_j + c_j x_{j+1} = d_j,
-// indices mod N, N a power of two; in place in LDS, solution left in d.
+// indices mod N, N a power of two; in place in LDS (row j at pad(j)),
+// solution left in d.
 // Level s (1, 2, ..., N/2) eliminates x_{j-s}, x_{j+s} from the equations
 // j = 0 mod 2s using equations j -+ s; the last level leaves one equation in
 // x_0 alone; back substitution then recovers j = s mod 2s from j -+ s.
@@ -221,9 +227,9 @@ __global__ __launch_bounds__(kFaceBlock) void k_fluid_faces(Globals G)
 // same order either way.
 __device__ __forceinline__ void lds_wave_order() { asm volatile("" ::: "memory"); }
 
-__device__ __forceinline__ void cr_eliminate(double* a, double* b, double* c, double* d, int N, int s, int j)
+__device__ __forceinline__ void cr_eliminate(double* a, double* b, double* c, double* d, int N, int s, int j0)
 {
-    const int jm = (j - s) & (N - 1), jp = (j + s) & (N - 1);
+    const int j = pad(j0), jm = pad((j0 - s) & (N - 1)), jp = pad((j0 + s) & (N - 1));
     const double al = -a[j] / b[jm];
     const double ga = -c[j] / b[jp];
     const double na = al * a[jm];
@@ -237,9 +243,9 @@ __device__ __forceinline__ void cr_eliminate(double* a, double* b, double* c, do
 }
 
 __device__ __forceinline__ void cr_substitute(const double* a, const double* b, const double* c, double* d, int N,
-                                              int s, int j)
+                                              int s, int j0)
 {
-    const int jm = (j - s) & (N - 1), jp = (j + s) & (N - 1);
+    const int j = pad(j0), jm = pad((j0 - s) & (N - 1)), jp = pad((j0 + s) & (N - 1));
     d[j] = (d[j] - a[j] * d[jm] - c[j] * d[jp]) / b[j];
 }
 
@@ -274,7 +280,7 @@ __device__ void cyclic_reduce(double* a, double* b, double* c, double* d, int N)
 
 __global__ __launch_bounds__(kSolveBlock) void k_fluid_solve(Globals G)
 {
-    __shared__ double A[kMaxCells], B[kMaxCells], Cc[kMaxCells], D[kMaxCells];
+    __shared__ double A[kPadCells], B[kPadCells], Cc[kPadCells], D[kPadCells];
     __shared__ float tab[kMaxTableRows * kCols];
     constexpr int kRows = kMaxCells / kSolveBlock;
     const int col = blockIdx.x;
@@ -316,10 +322,11 @@ __global__ __launch_bounds__(kSolveBlock) void k_fluid_solve(Globals G)
             const double Dp = G.Da[o + j], Dm = G.Da[o + jm];
             const double gep = double(gp) + Dp * double(G.dn[o + j]);
             const double gem = double(gm) + Dm * double(G.dn[o + jm]);
-            A[j] = -r * Dm;
-            B[j] = 1.0 + r * (Dm + Dp);
-            Cc[j] = -r * Dp;
-            D[j] = double(nj) + dt * double(Sn) - dt / dx * (gep - gem);
+            const int pj = pad(j);
+            A[pj] = -r * Dm;
+            B[pj] = 1.0 + r * (Dm + Dp);
+            Cc[pj] = -r * Dp;
+            D[pj] = double(nj) + dt * double(Sn) - dt / dx * (gep - gem);
             const double Kp = G.kap[o + j], Km = G.kap[o + jm];
             const double hep = double(hp) + Kp * double(G.dT[o + j]);
             const double hem = double(hm) + Km * double(G.dT[o + jm]);
@@ -330,7 +337,7 @@ __global__ __launch_bounds__(kSolveBlock) void k_fluid_solve(Globals G)
 #pragma unroll
     for (int k = 0; k < kRows; ++k) {
         const int j = threadIdx.x + k * kSolveBlock;
-        if (j < N) n[j] = fmaxf(float(D[j]), G.n_floor);
+        if (j < N) n[j] = fmaxf(float(D[pad(j)]), G.n_floor);
     }
     __syncthreads();   // new densities visible to the whole workgroup
     // energy-density system with T' = w' / (1.5 n')
@@ -341,17 +348,18 @@ __global__ __launch_bounds__(kSolveBlock) void k_fluid_solve(Globals G)
             const int jm = (j - 1) & (N - 1), jp = (j + 1) & (N - 1);
             const double Kp = G.kap[o + j], Km = G.kap[o + jm];
             const double mm = 1.5 * double(n[jm]), m0 = 1.5 * double(n[j]), mp = 1.5 * double(n[jp]);
-            A[j] = -r * Km / mm;
-            B[j] = 1.0 + r * (Km + Kp) / m0;
-            Cc[j] = -r * Kp / mp;
-            D[j] = rhs_w[k];
+            const int pj = pad(j);
+            A[pj] = -r * Km / mm;
+            B[pj] = 1.0 + r * (Km + Kp) / m0;
+            Cc[pj] = -r * Kp / mp;
+            D[pj] = rhs_w[k];
         }
     }
     cyclic_reduce(A, B, Cc, D, N);
 #pragma unroll
     for (int k = 0; k < kRows; ++k) {
         const int j = threadIdx.x + k * kSolveBlock;
-        if (j < N) w[j] = fmaxf(float(D[j]), 1.5f * n[j] * G.T_min);
+        if (j < N) w[j] = fmaxf(float(D[pad(j)]), 1.5f * n[j] * G.T_min);
     }
 }
 
@@ -359,16 +367,16 @@ __global__ __launch_bounds__(kSolveBlock) void k_fluid_solve(Globals G)
 __global__ __launch_bounds__(kSolveBlock) void k_cyclic(const double* a, const double* b, const double* c,
                                                         double* d, int N)
 {
-    __shared__ double A[kMaxCells], B[kMaxCells], Cc[kMaxCells], D[kMaxCells];
+    __shared__ double A[kPadCells], B[kPadCells], Cc[kPadCells], D[kPadCells];
     const int64_t o = int64_t(blockIdx.x) * N;
     for (int j = threadIdx.x; j < N; j += blockDim.x) {
-        A[j] = a[o + j];
-        B[j] = b[o + j];
-        Cc[j] = c[o + j];
-        D[j] = d[o + j];
+        A[pad(j)] = a[o + j];
+        B[pad(j)] = b[o + j];
+        Cc[pad(j)] = c[o + j];
+        D[pad(j)] = d[o + j];
     }
     cyclic_reduce(A, B, Cc, D, N);
-    for (int j = threadIdx.x; j < N; j += blockDim.x) d[o + j] = D[j];
+    for (int j = threadIdx.x; j < N; j += blockDim.x) d[o + j] = D[pad(j)];
 }
 
 }  // namespace pcfluid
