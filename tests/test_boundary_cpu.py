@@ -75,3 +75,21 @@ def test_batch_sizes_and_rules(native):
         native.query_batch_sizes([a, W.with_(b, dt=1e-6)])   # unstable member
     with pytest.raises(native.PcError):
         native.query_batch_sizes([])
+
+
+@pytest.mark.parametrize("cells,table_len,ok", [(4096, 120, True), (64, 2, True), (4096, 1024, True),
+                                                (4096, 1025, False), (4096, 1, False), (48, 120, False),
+                                                (8192, 120, False), (1000, 120, False)])
+def test_fluid_config_validation(native, cells, table_len, ok):
+    """Fluid columns: power-of-two cell counts in [64, 4096] (cyclic reduction)
+    and at most 1024 table rows (the kernels stage the table in LDS); checked
+    by the host-side workspace query, no GPU needed."""
+    import ctypes as C
+    from paper_2202_03215_amd import fluid as FL
+    cfg = FL.pc_fluid_config(4, cells, table_len, 0, 1e-9, 0.5, 0.125, 1e6)
+    nbytes = C.c_int64(0)
+    status = FL._lib().pc_fluid_query(C.byref(cfg), C.byref(nbytes))
+    if ok:
+        assert status == 0 and nbytes.value > 0
+    else:
+        assert status != 0
