@@ -55,12 +55,12 @@ def test_cyclic_tridiagonal_solve(torch_cuda, n, weak):
         assert np.abs(x[s] - ref).max() <= 1e-12 * np.abs(ref).max()
 
 
-def _columns(n_cells, table, dt):
+def _columns(n_cells, table, dt, T_step=W.FLUID_T_STEP):
     cols = []
     for k, (L, p, dE) in enumerate(((0.05, 1.0, 1.0), (0.08, 0.7, 1.15), (0.03, 1.5, 0.9))):
         Ng = 3.22e22 * p
         c = F.FluidColumn(n_cells=n_cells, L=L, Ngas=Ng, E0=0.0, nu_w=2.0e4 / p, muiN=4.0e21, dt=dt,
-                          T_min=W.FLUID_T_MIN, T_step=W.FLUID_T_STEP, table=table)
+                          T_min=W.FLUID_T_MIN, T_step=T_step, table=table)
         T0, E0 = F.steady_temperature(c)
         c.E0 = E0 * dE
         cols.append((c, T0))
@@ -79,10 +79,10 @@ def _state(cols, n_cells, seed):
     return np.array(ns), np.array(ws)
 
 
-def _batch(cols, n_cells, dt, table):
+def _batch(cols, n_cells, dt, table, T_step=W.FLUID_T_STEP):
     from paper_2202_03215_amd.fluid import FluidBatch
     spec = [dict(L=c.L, Ngas=c.Ngas, E0=c.E0, nu_w=c.nu_w, muiN=c.muiN) for c, _ in cols]
-    return FluidBatch(spec, n_cells, dt, table, W.FLUID_T_MIN, W.FLUID_T_STEP)
+    return FluidBatch(spec, n_cells, dt, table, W.FLUID_T_MIN, T_step)
 
 
 @pytest.mark.parametrize("n_cells,steps,tol", [(64, 1, 2e-5), (512, 1, 2e-5), (4096, 1, 2e-5), (256, 40, 2e-4)])
@@ -106,6 +106,32 @@ def test_fluid_steps_against_oracle(torch_cuda, n_cells, steps, tol):
         g, H, E = (t.cpu().numpy().astype(np.float64) for t in fb.faces())
         d = cols[0][0].diag
         assert np.abs(E[0] - d["E"]).max() <= 1e-4 * np.abs(d["E"]).max()
+
+
+def test_fluid_step_longest_table_against_oracle(torch_cuda):
+    """The kernels stage the table in LDS, at most 1024 rows: the smooth
+    table resampled on a T grid of 1024 rows over the same range, one step
+    of 4096 cells against the oracle on the same table (bound as above)."""
+    base = np.asarray(W.fluid_table_smooth(), dtype=np.float64)
+    K = 1024
+    T_base = W.FLUID_T_MIN + W.FLUID_T_STEP * np.arange(len(base))
+    T_step = (T_base[-1] - W.FLUID_T_MIN) / (K - 1)
+    T_new = W.FLUID_T_MIN + T_step * np.arange(K)
+    table = np.stack([np.interp(T_new, T_base, base[:, q]) for q in range(base.shape[1])], axis=1)
+    n_cells, dt = 4096, 2e-9
+    cols = _columns(n_cells, table, dt, T_step)
+    n0, w0 = _state(cols, n_cells, 7)
+    n0 = n0.astype(np.float32).astype(np.float64)
+    w0 = w0.astype(np.float32).astype(np.float64)
+    fb = _batch(cols, n_cells, dt, table, T_step)
+    fb.set_state(n0, w0)
+    fb.step(1)
+    ng, wg = (t.cpu().numpy().astype(np.float64) for t in fb.get_state())
+    for k, (c, _) in enumerate(cols):
+        n, w = F.run(c, n0[k], w0[k], 1)
+        Tg, To = wg[k] / (1.5 * ng[k]), w / (1.5 * n)
+        assert np.abs(ng[k] - n).max() <= 2e-5 * n.mean(), (k, np.abs(ng[k] - n).max() / n.mean())
+        assert np.abs(Tg - To).max() <= 2e-5 * To.mean(), (k, np.abs(Tg - To).max() / To.mean())
 
 
 def test_fluid_full_size_against_oracle(torch_cuda):
