@@ -14,6 +14,9 @@
 //                  collisional loss), backward-Euler diffusion of density and
 //                  of energy density as two cyclic tridiagonal systems in
 //                  FP64, solved by cyclic reduction in LDS
+//   k_fluid_step   both in one workgroup per column, for the closures whose
+//                  fluxes the face pass computes (table, multipliers); the
+//                  network flux closure runs faces, network and solve apart
 // State and face arrays are FP32; the tridiagonal systems are FP64.
 #include <hip/hip_runtime.h>
 
@@ -153,19 +156,63 @@ __device__ __forceinline__ FaceQ face(const Globals& G, const float* tab, const 
     return q;
 }
 
-__global__ __launch_bounds__(kFaceBlock) void k_fluid_faces(Globals G)
+// the values of one face that the solve uses
+struct FaceOut {
+    float E, Da, kap, dn, dT, gam, H;
+};
+
+// outputs of face f from its quantities q and the column's total flux
+// Gamma_T: E, the closure fluxes Gamma and H (table and multiplier closures)
+// and the network inputs (network closures) are stored; D_a, kappa, dn/dx and
+// dT/dx only when the solve runs as a kernel of its own (store_solver)
+__device__ __forceinline__ FaceOut face_out(const Globals& G, const FaceQ& q, float GT, float mui, int64_t f,
+                                            bool store_solver)
 {
-    __shared__ double sh[kFaceBlock / 64];
-    __shared__ float tab[kMaxTableRows * kCols];
-    const int col = blockIdx.x;
-    const ColDev C = G.cols[col];
+    FaceOut r;
+    r.E = -q.A + GT * q.B;
+    r.Da = mui * q.De / q.mue;
+    const float beta = 1.5f * q.Tf * q.mueps;
+    const float Gc = 1.5f * q.Tf * q.Deps;
+    const float dG = 1.5f * q.Deps + 1.5f * q.Tf * q.dDeps;
+    r.kap = q.nf * (dG - beta * q.dDe / q.mue);
+    r.dn = q.dn;
+    r.dT = q.dT;
+    r.gam = 0.0f;
+    r.H = 0.0f;
+    G.E[f] = r.E;
+    if (store_solver) {
+        G.Da[f] = r.Da;
+        G.kap[f] = r.kap;
+        G.dn[f] = q.dn;
+        G.dT[f] = q.dT;
+    }
+    if (G.mlp != kTable) {
+        const float x[5] = {q.nf, 1.5f * q.Tf, r.E, q.dn, 1.5f * q.dT};
+        float* xo = G.x + f * 5;
+#pragma unroll
+        for (int k = 0; k < 5; ++k) xo[k] = (x[k] - G.norm[k]) * G.norm[5 + k];
+    }
+    if (G.mlp != kNetFlux) {
+        const float eta = q.nf * (mui / q.mue) * q.dDe;
+        const float chi = Gc - beta * q.De / q.mue;
+        r.gam = -r.Da * q.dn - eta * q.dT - q.mue / (q.mue + mui) * GT;
+        r.H = -chi * q.dn - r.kap * q.dT - beta / (q.mue + mui) * GT;
+        G.gam[f] = r.gam;
+        G.H[f] = r.H;
+    }
+    return r;
+}
+
+// the faces j = tid + r * kFaceBlock of this workgroup's column, in two
+// passes (the column sums of A and B fix Gamma_T first); each face is
+// evaluated once and kept in registers between the passes
+__device__ __forceinline__ void faces_column(const Globals& G, const ColDev& C, const float* tab, double* sh,
+                                             FaceOut (&fo)[kFacesPerThread], bool store_solver)
+{
     const int N = G.N;
-    const float* n = G.n + int64_t(col) * N;
-    const float* w = G.w + int64_t(col) * N;
-    const int64_t o = int64_t(col) * N;
-    stage_table(G, tab);
-    // the thread's faces j = tid + r * blockDim.x, kept in registers for the
-    // second pass (Gamma_T needs the column sums of A and B first)
+    const int64_t o = int64_t(blockIdx.x) * N;
+    const float* n = G.n + o;
+    const float* w = G.w + o;
     FaceQ qs[kFacesPerThread];
     double sa = 0.0, sb = 0.0;
 #pragma unroll
@@ -186,32 +233,18 @@ __global__ __launch_bounds__(kFaceBlock) void k_fluid_faces(Globals G)
 #pragma unroll
     for (int r = 0; r < kFacesPerThread; ++r) {
         const int j = threadIdx.x + r * kFaceBlock;
-        if (j >= N) break;
-        const FaceQ& q = qs[r];
-        const float E = -q.A + GT * q.B;
-        const float Da = mui * q.De / q.mue;
-        const float beta = 1.5f * q.Tf * q.mueps;
-        const float Gc = 1.5f * q.Tf * q.Deps;
-        const float dG = 1.5f * q.Deps + 1.5f * q.Tf * q.dDeps;
-        const float kap = q.nf * (dG - beta * q.dDe / q.mue);
-        G.E[o + j] = E;
-        G.Da[o + j] = Da;
-        G.kap[o + j] = kap;
-        G.dn[o + j] = q.dn;
-        G.dT[o + j] = q.dT;
-        if (G.mlp != kTable) {
-            const float f[5] = {q.nf, 1.5f * q.Tf, E, q.dn, 1.5f * q.dT};
-            float* xo = G.x + (o + j) * 5;
-#pragma unroll
-            for (int k = 0; k < 5; ++k) xo[k] = (f[k] - G.norm[k]) * G.norm[5 + k];
-        }
-        if (G.mlp != kNetFlux) {
-            const float eta = q.nf * (mui / q.mue) * q.dDe;
-            const float chi = Gc - beta * q.De / q.mue;
-            G.gam[o + j] = -Da * q.dn - eta * q.dT - q.mue / (q.mue + mui) * GT;
-            G.H[o + j] = -chi * q.dn - kap * q.dT - beta / (q.mue + mui) * GT;
-        }
+        if (j < N) fo[r] = face_out(G, qs[r], GT, mui, o + j, store_solver);
     }
+}
+
+__global__ __launch_bounds__(kFaceBlock) void k_fluid_faces(Globals G)
+{
+    __shared__ double sh[kFaceBlock / 64];
+    __shared__ float tab[kMaxTableRows * kCols];
+    const ColDev C = G.cols[blockIdx.x];
+    stage_table(G, tab);
+    FaceOut fo[kFacesPerThread];
+    faces_column(G, C, tab, sh, fo, true);
 }
 
 // ---- cyclic reduction for a_j x_{j-1} + b_j x_j + c_j x_{j+1} = d_j,
@@ -290,28 +323,97 @@ __device__ void cyclic_reduce(double* a, double* b, double* c, double* d, int N)
     __syncthreads();
 }
 
+constexpr int kRows = kMaxCells / kSolveBlock;
+static_assert(kRows == kFacesPerThread, "a thread's cells are its faces' left cells");
+
+// explicit parts of cell j (sources, the closure fluxes' divergence): the
+// density row at pj and, returned, the energy right-hand side; faces p = j
+// (right of the cell) and m = j - 1
+__device__ __forceinline__ double setup_cell(const Globals& G, const ColDev& C, const float* tab, double r,
+                                             double dt, double dx, float nj, float wj, float gp, float gm,
+                                             float hp, float hm, float Ep, float Em, float Dap, float Dam, float dnp,
+                                             float dnm, float Kpf, float Kmf, float dTp, float dTm, int pj,
+                                             double* A, double* B, double* Cc, double* D)
+{
+    const float Ng = float(C.Ngas);
+    const Coef cc = interp(G, tab, wj / (1.5f * nj));
+    const float Sn = nj * (Ng * cc.v[4] - float(C.nu_w));
+    const float P = -0.5f * (gm * Em + gp * Ep);
+    const float Sw = P - nj * (Ng * cc.v[5]);
+    const double Dp = Dap, Dm = Dam;
+    const double gep = double(gp) + Dp * double(dnp);
+    const double gem = double(gm) + Dm * double(dnm);
+    A[pj] = -r * Dm;
+    B[pj] = 1.0 + r * (Dm + Dp);
+    Cc[pj] = -r * Dp;
+    D[pj] = double(nj) + dt * double(Sn) - dt / dx * (gep - gem);
+    const double Kp = Kpf, Km = Kmf;
+    const double hep = double(hp) + Kp * double(dTp);
+    const double hem = double(hm) + Km * double(dTm);
+    return double(wj) + dt * double(Sw) - dt / dx * (hep - hem);
+}
+
+// the density solve, then the energy-density system with T' = w' / (1.5 n')
+// and its solve; Kp, Km: kappa of each own cell's right and left faces
+__device__ __forceinline__ void solve_tail(const Globals& G, double* A, double* B, double* Cc, double* D,
+                                           const double (&rhs_w)[kRows], const float (&Kp)[kRows],
+                                           const float (&Km)[kRows], double r)
+{
+    const int N = G.N;
+    const int64_t o = int64_t(blockIdx.x) * N;
+    float* n = G.n + o;
+    float* w = G.w + o;
+    cyclic_reduce(A, B, Cc, D, N);
+#pragma unroll
+    for (int k = 0; k < kRows; ++k) {
+        const int j = threadIdx.x + k * kSolveBlock;
+        if (j < N) n[j] = fmaxf(float(D[pad(j)]), G.n_floor);
+    }
+    __syncthreads();   // new densities visible to the whole workgroup
+#pragma unroll
+    for (int k = 0; k < kRows; ++k) {
+        const int j = threadIdx.x + k * kSolveBlock;
+        if (j < N) {
+            const int jm = (j - 1) & (N - 1), jp = (j + 1) & (N - 1);
+            const double kp = Kp[k], km = Km[k];
+            const double mm = 1.5 * double(n[jm]), m0 = 1.5 * double(n[j]), mp = 1.5 * double(n[jp]);
+            const int pj = pad(j);
+            A[pj] = -r * km / mm;
+            B[pj] = 1.0 + r * (km + kp) / m0;
+            Cc[pj] = -r * kp / mp;
+            D[pj] = rhs_w[k];
+        }
+    }
+    cyclic_reduce(A, B, Cc, D, N);
+#pragma unroll
+    for (int k = 0; k < kRows; ++k) {
+        const int j = threadIdx.x + k * kSolveBlock;
+        if (j < N) w[j] = fmaxf(float(D[pad(j)]), 1.5f * n[j] * G.T_min);
+    }
+}
+
+// the solve as a kernel of its own, after the face kernel (and, with the
+// network flux closure, after the network): face values from memory
 __global__ __launch_bounds__(kSolveBlock) void k_fluid_solve(Globals G)
 {
     __shared__ double A[kPadCells], B[kPadCells], Cc[kPadCells], D[kPadCells];
     __shared__ float tab[kMaxTableRows * kCols];
-    constexpr int kRows = kMaxCells / kSolveBlock;
-    const int col = blockIdx.x;
-    const ColDev C = G.cols[col];
+    const ColDev C = G.cols[blockIdx.x];
     const int N = G.N;
-    const int64_t o = int64_t(col) * N;
-    float* n = G.n + o;
-    float* w = G.w + o;
+    const int64_t o = int64_t(blockIdx.x) * N;
+    const float* n = G.n + o;
+    const float* w = G.w + o;
     const double dx = C.L / double(N);
     const double dt = double(G.dt);
     const double r = dt / (dx * dx);
-    const float Ng = float(C.Ngas);
     stage_table(G, tab);
     double rhs_w[kRows];
-    // density system and the energy right-hand side (explicit parts)
+    float Kp[kRows], Km[kRows];
 #pragma unroll
     for (int k = 0; k < kRows; ++k) {
         const int j = threadIdx.x + k * kSolveBlock;
         rhs_w[k] = 0.0;
+        Kp[k] = Km[k] = 0.0f;
         if (j < N) {
             const int jm = (j - 1) & (N - 1);
             float gp, gm, hp, hm;
@@ -326,53 +428,93 @@ __global__ __launch_bounds__(kSolveBlock) void k_fluid_solve(Globals G)
                 hp = G.H[o + j];
                 hm = G.H[o + jm];
             }
-            const float nj = n[j], wj = w[j];
-            const Coef cc = interp(G, tab, wj / (1.5f * nj));
-            const float Sn = nj * (Ng * cc.v[4] - float(C.nu_w));
-            const float P = -0.5f * (gm * G.E[o + jm] + gp * G.E[o + j]);
-            const float Sw = P - nj * (Ng * cc.v[5]);
-            const double Dp = G.Da[o + j], Dm = G.Da[o + jm];
-            const double gep = double(gp) + Dp * double(G.dn[o + j]);
-            const double gem = double(gm) + Dm * double(G.dn[o + jm]);
-            const int pj = pad(j);
-            A[pj] = -r * Dm;
-            B[pj] = 1.0 + r * (Dm + Dp);
-            Cc[pj] = -r * Dp;
-            D[pj] = double(nj) + dt * double(Sn) - dt / dx * (gep - gem);
-            const double Kp = G.kap[o + j], Km = G.kap[o + jm];
-            const double hep = double(hp) + Kp * double(G.dT[o + j]);
-            const double hem = double(hm) + Km * double(G.dT[o + jm]);
-            rhs_w[k] = double(wj) + dt * double(Sw) - dt / dx * (hep - hem);
+            Kp[k] = G.kap[o + j];
+            Km[k] = G.kap[o + jm];
+            rhs_w[k] = setup_cell(G, C, tab, r, dt, dx, n[j], w[j], gp, gm, hp, hm, G.E[o + j], G.E[o + jm],
+                                  G.Da[o + j], G.Da[o + jm], G.dn[o + j], G.dn[o + jm], Kp[k], Km[k], G.dT[o + j],
+                                  G.dT[o + jm], pad(j), A, B, Cc, D);
         }
     }
-    cyclic_reduce(A, B, Cc, D, N);
-#pragma unroll
-    for (int k = 0; k < kRows; ++k) {
-        const int j = threadIdx.x + k * kSolveBlock;
-        if (j < N) n[j] = fmaxf(float(D[pad(j)]), G.n_floor);
-    }
-    __syncthreads();   // new densities visible to the whole workgroup
-    // energy-density system with T' = w' / (1.5 n')
+    solve_tail(G, A, B, Cc, D, rhs_w, Kp, Km, r);
+}
+
+// faces and solve of one column in one workgroup (table and multiplier
+// closures, whose fluxes the face pass computes): each cell's right face is
+// the thread's own, its left face the neighbouring thread's, handed over
+// through LDS that the tridiagonal systems take over afterwards.  The same
+// arithmetic as the face kernel followed by the solve kernel, without the
+// face arrays only the solve reads, their reload, a second table staging and
+// a launch.
+constexpr int kFaceVals = 7;
+static_assert(kFaceVals * kMaxCells * sizeof(float) <= 4 * kPadCells * sizeof(double),
+              "the face hand-over fits in the systems' LDS");
+__global__ __launch_bounds__(kSolveBlock) void k_fluid_step(Globals G)
+{
+    __shared__ double sys[4 * kPadCells];
+    __shared__ float tab[kMaxTableRows * kCols];
+    __shared__ double sh[kFaceBlock / 64];
+    double* A = sys;
+    double* B = sys + kPadCells;
+    double* Cc = sys + 2 * kPadCells;
+    double* D = sys + 3 * kPadCells;
+    float* X = reinterpret_cast<float*>(sys);   // [kFaceVals][N], before the systems are set up
+    const ColDev C = G.cols[blockIdx.x];
+    const int N = G.N;
+    const int64_t o = int64_t(blockIdx.x) * N;
+    const float* n = G.n + o;
+    const float* w = G.w + o;
+    const double dx = C.L / double(N);
+    const double dt = double(G.dt);
+    const double r = dt / (dx * dx);
+    stage_table(G, tab);
+    FaceOut fo[kFacesPerThread];
+    faces_column(G, C, tab, sh, fo, false);
 #pragma unroll
     for (int k = 0; k < kRows; ++k) {
         const int j = threadIdx.x + k * kSolveBlock;
         if (j < N) {
-            const int jm = (j - 1) & (N - 1), jp = (j + 1) & (N - 1);
-            const double Kp = G.kap[o + j], Km = G.kap[o + jm];
-            const double mm = 1.5 * double(n[jm]), m0 = 1.5 * double(n[j]), mp = 1.5 * double(n[jp]);
-            const int pj = pad(j);
-            A[pj] = -r * Km / mm;
-            B[pj] = 1.0 + r * (Km + Kp) / m0;
-            Cc[pj] = -r * Kp / mp;
-            D[pj] = rhs_w[k];
+            X[0 * N + j] = fo[k].E;
+            X[1 * N + j] = fo[k].Da;
+            X[2 * N + j] = fo[k].kap;
+            X[3 * N + j] = fo[k].dn;
+            X[4 * N + j] = fo[k].dT;
+            X[5 * N + j] = fo[k].gam;
+            X[6 * N + j] = fo[k].H;
         }
     }
-    cyclic_reduce(A, B, Cc, D, N);
+    __syncthreads();
+    FaceOut fm[kRows];   // face j - 1 of each own cell j
 #pragma unroll
     for (int k = 0; k < kRows; ++k) {
         const int j = threadIdx.x + k * kSolveBlock;
-        if (j < N) w[j] = fmaxf(float(D[pad(j)]), 1.5f * n[j] * G.T_min);
+        if (j < N) {
+            const int jm = (j - 1) & (N - 1);
+            fm[k].E = X[0 * N + jm];
+            fm[k].Da = X[1 * N + jm];
+            fm[k].kap = X[2 * N + jm];
+            fm[k].dn = X[3 * N + jm];
+            fm[k].dT = X[4 * N + jm];
+            fm[k].gam = X[5 * N + jm];
+            fm[k].H = X[6 * N + jm];
+        }
     }
+    __syncthreads();   // the hand-over is read before the systems overwrite it
+    double rhs_w[kRows];
+    float Kp[kRows], Km[kRows];
+#pragma unroll
+    for (int k = 0; k < kRows; ++k) {
+        const int j = threadIdx.x + k * kSolveBlock;
+        rhs_w[k] = 0.0;
+        Kp[k] = Km[k] = 0.0f;
+        if (j < N) {
+            Kp[k] = fo[k].kap;
+            Km[k] = fm[k].kap;
+            rhs_w[k] = setup_cell(G, C, tab, r, dt, dx, n[j], w[j], fo[k].gam, fm[k].gam, fo[k].H, fm[k].H,
+                                  fo[k].E, fm[k].E, fo[k].Da, fm[k].Da, fo[k].dn, fm[k].dn, Kp[k], Km[k], fo[k].dT,
+                                  fm[k].dT, pad(j), A, B, Cc, D);
+        }
+    }
+    solve_tail(G, A, B, Cc, D, rhs_w, Kp, Km, r);
 }
 
 // stand-alone batched cyclic tridiagonal solve (device arrays [ns][N]); x -> d
@@ -563,16 +705,25 @@ pc_status pc_fluid_step(pc_fluid_handle h, int64_t n_steps)
     const int nc = h->cfg.n_columns;
     const int64_t cells = int64_t(nc) * h->cfg.n_cells;
     for (int64_t k = 0; k < n_steps; ++k) {
-        hipLaunchKernelGGL(k_fluid_faces, dim3(nc), dim3(kFaceBlock), 0, h->st, h->G);
-        if (h->G.mlp != kTable) {
-            // fluxes of this step, or the multipliers of the next one (the
-            // face kernel above has read the previous answer)
+        if (h->G.mlp == kNetFlux) {
+            // the network gives this step's fluxes: faces, network, solve
+            hipLaunchKernelGGL(k_fluid_faces, dim3(nc), dim3(kFaceBlock), 0, h->st, h->G);
             const pc_status s = pc_mlp_forward(h->mlp_packed, h->G.x, cells, const_cast<float*>(h->G.y), nullptr,
                                                h->st);
             if (s != PC_OK) return s;
+            hipLaunchKernelGGL(k_fluid_solve, dim3(nc), dim3(kSolveBlock), 0, h->st, h->G);
+        } else {
+            // table fluxes (with the multipliers of the previous answer):
+            // faces and solve in one kernel; the network then gives the
+            // multipliers of the next step from this step's face inputs
+            hipLaunchKernelGGL(k_fluid_step, dim3(nc), dim3(kSolveBlock), 0, h->st, h->G);
+            if (h->G.mlp == kNetMult) {
+                const pc_status s = pc_mlp_forward(h->mlp_packed, h->G.x, cells, const_cast<float*>(h->G.y),
+                                                   nullptr, h->st);
+                if (s != PC_OK) return s;
+                h->G.have_m = 1;
+            }
         }
-        hipLaunchKernelGGL(k_fluid_solve, dim3(nc), dim3(kSolveBlock), 0, h->st, h->G);
-        if (h->G.mlp == kNetMult) h->G.have_m = 1;
     }
     return hipGetLastError() == hipSuccess ? PC_OK : ferr(PC_ERR_HIP, "pc_fluid_step launch");
 }
